@@ -1,0 +1,202 @@
+"""Pins of the oracle's source-term graph and greedy dominating set (Sec. 3)
+against brute force, hand-checkable graphs and the greedy-choice property,
+all computed here with plain Python loops that share nothing with
+``oracle.tree``."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import tree as ot
+from paper_1411_3691_amd import workloads as W
+
+
+def plain_neighbours(terms):
+    n = len(terms)
+    nb = [set() for _ in range(n)]
+    for i in range(n):
+        for j in range(n):
+            if i != j and sum(int(a != b) for a, b in zip(terms[i], terms[j])) == 1:
+                nb[i].add(j)
+    return nb
+
+
+def random_terms(seed, n=60, sn=4, M=5):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, M, size=(n, sn))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_hamming_pairs_brute_force(seed):
+    terms = random_terms(seed)
+    nb = plain_neighbours(terms.tolist())
+    e = ot.hamming1_pairs(terms)
+    got = {(int(a), int(b)) for a, b in e}
+    want = {(i, j) for i in range(len(terms)) for j in nb[i] if i < j}
+    assert got == want
+
+
+def replay_r2(terms, tree):
+    """Check every step of R2 against gains recomputed with plain loops."""
+    nb = plain_neighbours(terms.tolist())
+    n = len(terms)
+    covered = [False] * n
+    owner = [-1] * n
+    for step in range(tree["n_dom"]):
+        gains = [int(not covered[v]) + sum(1 for u in nb[v] if not covered[u])
+                 for v in range(n)]
+        best = max(gains)
+        v = gains.index(best)        # lowest index among the maxima
+        assert int(tree["dom_order"][step]) == v, step
+        for u in [v] + sorted(nb[v]):
+            if not covered[u]:
+                covered[u] = True
+                owner[u] = v
+        owner[v] = v
+    assert all(covered)
+    assert list(tree["owner"]) == owner
+
+
+def replay_r1(terms, tree):
+    nb = plain_neighbours(terms.tolist())
+    n = len(terms)
+    remaining = set(range(n))
+    owner = [-1] * n
+    for step in range(tree["n_dom"]):
+        degs = {v: sum(1 for u in nb[v] if u in remaining) for v in remaining}
+        best = max(degs.values())
+        v = min(u for u in remaining if degs[u] == best)
+        assert int(tree["dom_order"][step]) == v, step
+        owner[v] = v
+        remaining.discard(v)
+        for u in nb[v]:
+            if u in remaining:
+                owner[u] = v
+                remaining.discard(u)
+    assert not remaining
+    assert list(tree["owner"]) == owner
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_r2_greedy_choice_property(seed):
+    terms = random_terms(seed, n=80)
+    tree = ot.build(terms, (2, 2), policy=ot.R2)
+    replay_r2(terms, tree)
+
+
+@pytest.mark.parametrize("seed", [6, 7])
+def test_r1_greedy_choice_property_and_independence(seed):
+    terms = random_terms(seed, n=80)
+    tree = ot.build(terms, (2, 2), policy=ot.R1)
+    replay_r1(terms, tree)
+    nb = plain_neighbours(terms.tolist())
+    doms = [int(d) for d in tree["dom_order"][:tree["n_dom"]]]
+    for a, b in itertools.combinations(doms, 2):
+        assert b not in nb[a]
+
+
+def check_invariants(terms, nf, tree):
+    n = len(terms)
+    offs = np.concatenate([[0], np.cumsum(nf)])
+    doms = set(int(d) for d in tree["dom_order"][:tree["n_dom"]])
+    assert len(doms) == tree["n_dom"]
+    assert all(int(d) == -1 for d in tree["dom_order"][tree["n_dom"]:])
+    for u in range(n):
+        d = int(tree["owner"][u])
+        if u in doms:
+            assert d == u and tree["flav"][u] == -1 and tree["pos"][u] == -1
+            continue
+        assert d in doms
+        diff = [p for p in range(len(terms[u])) if terms[u][p] != terms[d][p]]
+        assert len(diff) == 1
+        f = int(tree["flav"][u])
+        assert offs[f] + int(tree["pos"][u]) == diff[0]
+        assert 0 <= tree["pos"][u] < nf[f]
+
+
+def test_special_graphs():
+    # star: one centre, leaves differ from it in one position each and from
+    # each other in two -> a single dominator (the centre, index 3)
+    centre = [0, 1, 2, 3]
+    star = [[5, 1, 2, 3], [0, 6, 2, 3], [0, 1, 7, 3], centre, [0, 1, 2, 8]]
+    for pol in (ot.R1, ot.R2):
+        t = ot.build(np.array(star), (2, 2), policy=pol)
+        assert t["n_dom"] == 1 and t["dom_order"][0] == 3
+        check_invariants(star, (2, 2), t)
+    # clique of same-position siblings: complete graph -> lowest index wins
+    clique = np.array([[c, 1, 2, 3] for c in (4, 5, 6, 7, 0)])
+    t = ot.build(clique, (2, 2))
+    assert t["n_dom"] == 1 and t["dom_order"][0] == 0
+    assert list(t["pos"]) == [-1, 0, 0, 0, 0] and list(t["flav"]) == [-1, 0, 0, 0, 0]
+    # no edges: every term is its own dominator, in index order
+    far = np.array([[i, i + 10, i + 20, i + 30] for i in range(6)])
+    t = ot.build(far, (2, 2))
+    assert t["n_dom"] == 6 and list(t["dom_order"]) == list(range(6))
+    # duplicates are at distance 0: not neighbours of each other
+    dup = np.array([[0, 1, 2, 3], [0, 1, 2, 3]])
+    t = ot.build(dup, (2, 2))
+    assert t["n_dom"] == 2
+    # path a-b-c-d-e (each step changes one position, ends are far apart)
+    path = np.array([[0, 0, 0, 0], [1, 0, 0, 0], [1, 1, 0, 0], [1, 1, 1, 0], [1, 1, 1, 1]])
+    t = ot.build(path, (2, 2), policy=ot.R2)
+    # gains: 2,3,3,3,2 -> pick 1 (covers 0,1,2), then gains of 3 and 4... 3 covers {3,4}
+    assert list(t["dom_order"][:t["n_dom"]]) == [1, 3]
+    assert list(t["owner"]) == [1, 1, 1, 3, 3]
+    t = ot.build(path, (2, 2), policy=ot.R1)
+    assert list(t["dom_order"][:t["n_dom"]]) == [1, 3]
+
+
+def test_r2_can_promote_a_covered_vertex():
+    # 0 covers 1 and 2; later 1 (already covered) is the best choice to
+    # cover 3, 4, 5, so it becomes a dominator and leaves 0's children.
+    terms = np.array([
+        [0, 0, 0, 0],   # 0
+        [1, 0, 0, 0],   # 1  (nb of 0)
+        [0, 1, 0, 0],   # 2  (nb of 0)
+        [1, 2, 0, 0],   # 3  (nb of 1)
+        [1, 0, 2, 0],   # 4  (nb of 1)
+        [1, 0, 0, 2],   # 5  (nb of 1)
+        [0, 0, 3, 0],   # 6  (nb of 0)
+        [0, 0, 0, 3],   # 7  (nb of 0)
+    ])
+    t = ot.build(terms, (2, 2), policy=ot.R2)
+    replay_r2(terms, t)
+    check_invariants(terms, (2, 2), t)
+    assert list(t["dom_order"][:t["n_dom"]]) == [0, 1]
+    assert t["owner"][1] == 1 and t["owner"][3] == 1 and t["owner"][2] == 0
+
+
+def test_greedy_close_to_minimum_on_tiny_graphs():
+    # R2 is the set-cover greedy: |D| <= H(max closed degree) * |D_min|.
+    rng = np.random.default_rng(21)
+    for _ in range(5):
+        terms = rng.integers(0, 3, size=(11, 3))
+        terms = np.unique(terms, axis=0)
+        nb = plain_neighbours(terms.tolist())
+        n = len(terms)
+        best = None
+        for k in range(1, n + 1):
+            for D in itertools.combinations(range(n), k):
+                cov = set(D)
+                for v in D:
+                    cov |= nb[v]
+                if len(cov) == n:
+                    best = k
+                    break
+            if best:
+                break
+        t = ot.build(terms, (1, 2))
+        delta = max(len(s) for s in nb) + 1
+        H = sum(1.0 / k for k in range(1, delta + 1))
+        assert best <= t["n_dom"] <= H * best + 1e-9
+
+
+def test_workload_tree_statistics():
+    # Synthetic "mid" source terms (2000 terms of 2 x 6 quarks): the greedy
+    # leaves roughly one term in eight as a dominator, inside the range of
+    # dominating-set fractions the paper reports (Sec. 4, about 0.09-0.13).
+    w = W.workload("mid", T=1)
+    t = ot.build(w.src, w.nf)
+    check_invariants(w.src, w.nf, t)
+    rho = t["n_dom"] / len(w.src)
+    assert 0.08 <= rho <= 0.14
