@@ -1,0 +1,158 @@
+/*
+ * mhc.h -- multi-hadron correlator contraction on MI355X (gfx950).
+ *
+ * C ABI of libmhc.so.  For each time slice t the library evaluates
+ *
+ *     C(t) = sum_{i in src} sum_{j in snk} w_i w'_j prod_f det G_f^(ij)(t),
+ *     G_f^(ij)(t)[m][n] = S_t[a_i^{f,m}][a_j^{f,n}],
+ *
+ * (Vachaspati & Detmold, "Fast Evaluation of Multi-Hadron Correlation
+ * Functions", Sec. 1: the correlator as a weighted double sum of
+ * determinants, with G block diagonal over quark flavours), either with one
+ * pivoted LU per pair and flavour, or with the update tree of Secs. 2-3: a
+ * greedy dominating set of the source terms gets LU factorisations, and
+ * every other source term is one rank-1 row update away from its dominator
+ * (matrix determinant lemma, one shared solve per changed row).
+ *
+ * Conventions for every function:
+ *  - The return value is an mhc_status: MHC_OK (0) or a negative code.  On
+ *    error mhc_last_error() returns a message for the calling thread.  No
+ *    C++ exception crosses the ABI.
+ *  - Host-detectable errors (NULL arguments, shapes, invalid terms) are
+ *    reported before anything is enqueued on a stream.
+ *  - *_create functions copy every host input; the caller may free its
+ *    arrays afterwards.  Handles belong to the library until *_destroy.
+ *    *_destroy(NULL) is a no-op.
+ *  - Device buffers are caller-owned, contiguous and on the device that was
+ *    current when the plan was created.  complex128 means interleaved
+ *    (re, im) doubles, the layout of torch.complex128 and hipDoubleComplex.
+ *  - A stream argument is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls that take a stream enqueue work and return without
+ *    synchronising.
+ *  - A handle must not be used from two threads at once; different handles
+ *    are independent.
+ */
+#ifndef MHC_H
+#define MHC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MHC_OK = 0,
+  MHC_E_ARG = -1,         /* NULL pointer or out-of-range scalar argument    */
+  MHC_E_TERM = -2,        /* invalid wavefunction term (index range/repeat)  */
+  MHC_E_SHAPE = -3,       /* inconsistent shapes between handles/arguments   */
+  MHC_E_DEVICE = -4,      /* HIP runtime error                               */
+  MHC_E_OOM = -5,         /* host or device allocation failed                */
+  MHC_E_STATE = -6,       /* handle in the wrong state for this call         */
+  MHC_E_UNSUPPORTED = -7  /* valid input outside what the kernels implement  */
+} mhc_status;
+
+/* Greedy dominating-set rules (Sec. 3).
+ * R2 (default): set-cover greedy on closed neighbourhoods -- every term
+ *   stays eligible; each step takes the term whose closed neighbourhood holds
+ *   the most still-uncovered terms (lowest index on ties).
+ * R1: the literal rule -- take the remaining term of highest degree in the
+ *   graph of remaining terms (lowest index on ties), then remove it and its
+ *   remaining neighbours. */
+enum { MHC_GREEDY_R1 = 1, MHC_GREEDY_R2 = 2 };
+
+/* Contraction methods. */
+enum {
+  MHC_PLAIN_LU = 0,    /* pivoted LU of every pair and flavour block (Sec. 2) */
+  MHC_UPDATE_TREE = 1  /* dominator LU + rank-1 updates (Secs. 2-3)           */
+};
+
+typedef struct mhc_terms mhc_terms;
+typedef struct mhc_tree mhc_tree;
+typedef struct mhc_plan mhc_plan;
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* mhc_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int32_t mhc_version(void);
+
+/* Wavefunction terms (Sec. 1: each term is a product of quark creation
+ * operators with a weight; the weight tensor is antisymmetric, so it
+ * vanishes when an index repeats).
+ *   n_terms      >= 1
+ *   n_flavors    in [1, 8]; n_per_flavor[f] in [1, 32]
+ *   idx          host int32 [n_terms][sum_f n_per_flavor[f]], flavour-major:
+ *                the first n_per_flavor[0] entries of a term are its flavour-0
+ *                quark indices, in order, then flavour 1, ...
+ *   M            size of the quark index space, in [1, 255]; every index
+ *                must lie in [0, M)
+ * A term with an index outside [0, M), or with a repeated index within one
+ * flavour, is rejected with MHC_E_TERM (its weight would be zero).
+ * Weights are not part of the terms: they are passed to each contraction. */
+mhc_status mhc_terms_create(int32_t n_terms, int32_t n_flavors,
+                            const int32_t* n_per_flavor, const int32_t* idx,
+                            int32_t M, mhc_terms** out);
+void mhc_terms_destroy(mhc_terms* terms);
+/* Shape queries (any pointer may be NULL). */
+mhc_status mhc_terms_shape(const mhc_terms* terms, int32_t* n_terms,
+                           int32_t* n_flavors, int32_t* M);
+
+/* Update tree over source terms (Sec. 3).  Two terms are neighbours when
+ * their index tuples differ in exactly one position; that position is the
+ * flavour block f and the row r that changes (Sec. 2: G^(jk) = G^(ik) +
+ * e_r v^T).  The greedy rule `policy` picks dominators; every other term
+ * becomes a child of the first dominator whose neighbourhood covered it.
+ * Host only; depends on neither S nor the weights, so one tree serves every
+ * gauge configuration and time slice. */
+mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
+                          mhc_tree** out);
+/* Copy the tree out (host arrays of n_terms int32 each, any may be NULL):
+ *   n_dom            number of dominators
+ *   dom_order[k]     k-th dominator chosen (k < n_dom), -1 after that
+ *   owner[u]         dominator owning term u (owner[d] == d for dominators)
+ *   flav[u], pos[u]  flavour block and row in which u differs from its
+ *                    owner; -1 for dominators */
+mhc_status mhc_tree_export(const mhc_tree* tree, int32_t* n_dom,
+                           int32_t* dom_order, int32_t* owner, int32_t* flav,
+                           int32_t* pos);
+/* Counts: dominators, (dominator, flavour, row) groups, children. */
+mhc_status mhc_tree_stats(const mhc_tree* tree, int32_t* n_dom,
+                          int32_t* n_groups, int32_t* n_children);
+void mhc_tree_destroy(mhc_tree* tree);
+
+/* Device plan: the source tree and the sink terms uploaded once to the
+ * current HIP device (Sec. 3: built once and reused across configurations).
+ * Both term sets must have the same flavour structure and M.  Enqueues the
+ * uploads on `stream`. */
+mhc_status mhc_plan_create(const mhc_tree* src_tree, const mhc_terms* snk,
+                           void* stream, mhc_plan** out);
+void mhc_plan_destroy(mhc_plan* plan);
+
+/* Forward contraction.  Device pointers, caller-owned:
+ *   S         complex128 [T][M][M], row = source quark index, column = sink
+ *             quark index (Sec. 1)
+ *   w_src     double [n_src];  w_snk  double [n_snk]
+ *   C         complex128 [T] (output)
+ *   A         double [T] or NULL: A(t) = sum_ij |w_i w'_j d_ij(t)| (output;
+ *             the scale the result's accuracy is judged against)
+ *   pair_det  complex128 [T][n_src][n_snk] or NULL: every d_ij(t) =
+ *             prod_f det G_f^(ij)(t) (output; a test hook)
+ * T >= 1.  method is MHC_PLAIN_LU or MHC_UPDATE_TREE; both return the same
+ * quantities within floating-point rounding.  Every pointer must stay valid
+ * until the stream has run the work. */
+mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
+                        const void* S, const double* w_src,
+                        const double* w_snk, void* C, double* A,
+                        void* pair_det, void* stream);
+
+/* Number of (pair, flavour, child) determinants that the update path took
+ * by direct LU because the dominator's factorisation had an exactly zero
+ * pivot, summed over all completed calls on this plan.  Synchronises the
+ * device first. */
+mhc_status mhc_plan_status(mhc_plan* plan, int64_t* n_fallback);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHC_H */

@@ -108,12 +108,24 @@ def correlator(S, src, snk, nf, w_src, w_snk, slices=None):
 
 def condition_1norm(G) -> np.ndarray:
     """kappa_1(G) = ||G||_1 ||G^-1||_1 for a batch [..., n, n] (used only to
-    decide which tolerance a checked determinant is held to)."""
+    decide which tolerance a checked determinant is held to); inf for an
+    exactly singular matrix."""
     G = np.asarray(G)
-    inv = np.linalg.inv(G)
-    n1 = np.abs(G).sum(axis=-2).max(axis=-1)
-    ni = np.abs(inv).sum(axis=-2).max(axis=-1)
-    return n1 * ni
+    shape = G.shape[:-2]
+    n = G.shape[-1]
+    flat = G.reshape(-1, n, n)
+    n1 = np.abs(flat).sum(axis=-2).max(axis=-1)
+    try:
+        inv = np.linalg.inv(flat)
+        ni = np.abs(inv).sum(axis=-2).max(axis=-1)
+    except np.linalg.LinAlgError:
+        ni = np.empty(len(flat))
+        for b in range(len(flat)):
+            try:
+                ni[b] = np.abs(np.linalg.inv(flat[b])).sum(axis=-2).max()
+            except np.linalg.LinAlgError:
+                ni[b] = np.inf
+    return (n1 * ni).reshape(shape)
 
 
 def pair_condition(S, src, snk, nf, t, i_idx, j_idx) -> np.ndarray:
@@ -131,9 +143,6 @@ def pair_condition(S, src, snk, nf, t, i_idx, j_idx) -> np.ndarray:
         b = snk[j_idx, o[f]:o[f + 1]]
         G = S[t[:, None, None], a[:, :, None], b[:, None, :]]
         with np.errstate(all="ignore"):
-            try:
-                k = condition_1norm(G)
-            except np.linalg.LinAlgError:
-                k = np.full(t.shape, np.inf)
+            k = condition_1norm(G)
         kap = np.maximum(kap, np.nan_to_num(k, nan=np.inf))
     return kap

@@ -1,0 +1,47 @@
+// Device-side views of a plan and the launcher of the contraction kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mhc {
+namespace kern {
+
+// Device tables of a plan (all pointers are device memory).
+struct PlanView {
+  int32_t n_src, n_snk, n_snk_pad, M, F, sn, n_dom;
+  int32_t off[9];                 // flavour offsets into a term's tuple
+  // update tree, dominators in greedy order
+  const int32_t* dom_term;        // [n_dom] source term of each dominator
+  const uint32_t* dom_rowoff;     // [n_dom][sn] byte offset a*M*16 of each row
+  const int32_t* dom_grp;         // [n_dom+1] group range of each dominator
+  const int32_t* grp_fr;          // [n_groups] (f << 8) | r
+  const int32_t* grp_ptr;         // [n_groups+1] child range of each group
+  const uint32_t* child_rowoff;   // [n_children] byte offset of the new row
+  const int32_t* child_term;      // [n_children] source term of the child
+  // plain method: every source term is its own row set
+  const uint32_t* src_rowoff;     // [n_src][sn]
+  // sinks, position-major for coalesced loads; padded sinks repeat sink 0
+  const uint32_t* snk_coloff;     // [sn][n_snk_pad] byte offset b*16
+};
+
+struct ContractArgs {
+  PlanView plan;
+  const double2* S;               // [T][M][M]
+  const double* w_src;            // [n_src]
+  const double* w_snk;            // [n_snk]
+  double* partial;                // [T][n_blk_t][3] workgroup partials
+  double2* pair_det;              // [T][n_src][n_snk] or null
+  unsigned long long* fallback;   // fallback counter or null
+  int T, n_items, n_blk_t, n_sblk;
+};
+
+// Enqueues the contraction of all T slices (n = block size of every
+// flavour) and the final reduction into C[T] (and A[T] if non-null).
+// diag selects the kernels that also produce A and pair determinants.
+hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag,
+                           double2* C, double* A, hipStream_t s);
+
+}  // namespace kern
+}  // namespace mhc

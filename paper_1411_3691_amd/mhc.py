@@ -1,0 +1,195 @@
+"""Python API over the libmhc C ABI.
+
+    terms_src = Terms(idx_src, nf, M)     # host int arrays [N][sum(nf)]
+    tree = Tree(terms_src)                # greedy dominating set (Sec. 3)
+    plan = Plan(tree, Terms(idx_snk, nf, M))
+    C = contract(plan, S, w_src, w_snk, method="tree")   # complex128 [T]
+
+Every step of the contraction runs in the library's HIP kernels; this
+module only converts arguments (torch tensors on the plan's device, numpy
+arrays for terms) into the pointers and sizes the C functions take.  There
+is no CPU fallback: without the built library or a GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+METHODS = {"plain": _lib.PLAIN_LU, "tree": _lib.UPDATE_TREE}
+POLICIES = {"R1": _lib.GREEDY_R1, "R2": _lib.GREEDY_R2}
+
+
+def _i32p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class Terms:
+    """Wavefunction terms: int [n_terms][sum(nf)], flavour-major."""
+
+    def __init__(self, idx, nf, M: int):
+        idx = np.ascontiguousarray(np.asarray(idx), dtype=np.int32)
+        nfa = np.ascontiguousarray(np.asarray(nf), dtype=np.int32)
+        if idx.ndim != 2 or idx.shape[1] != int(nfa.sum()):
+            raise ValueError("idx must be [n_terms][sum(nf)]")
+        self.idx = idx
+        self.nf = tuple(int(v) for v in nfa)
+        self.M = int(M)
+        h = ctypes.c_void_p()
+        check(lib().mhc_terms_create(idx.shape[0], len(nfa), _i32p(nfa),
+                                     _i32p(idx), int(M), ctypes.byref(h)))
+        self._h = h
+        self._destroy = lib().mhc_terms_destroy
+
+    def __len__(self):
+        return self.idx.shape[0]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._destroy(h)
+            self._h = None
+
+
+class Tree:
+    """Update tree over source terms (host only)."""
+
+    def __init__(self, terms: Terms, policy: str = "R2"):
+        self.terms = terms
+        self.policy = policy
+        h = ctypes.c_void_p()
+        check(lib().mhc_tree_build(terms.handle, POLICIES[policy], ctypes.byref(h)))
+        self._h = h
+        self._destroy = lib().mhc_tree_destroy
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self) -> dict:
+        n = len(self.terms)
+        n_dom = ctypes.c_int32()
+        arrs = {k: np.empty(n, dtype=np.int32) for k in ("dom_order", "owner", "flav", "pos")}
+        check(lib().mhc_tree_export(self._h, ctypes.byref(n_dom), _i32p(arrs["dom_order"]),
+                                    _i32p(arrs["owner"]), _i32p(arrs["flav"]),
+                                    _i32p(arrs["pos"])))
+        arrs["n_dom"] = int(n_dom.value)
+        return arrs
+
+    def stats(self) -> dict:
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().mhc_tree_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(n_dom=a.value, n_groups=b.value, n_children=c.value,
+                    n_terms=len(self.terms))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._destroy(h)
+            self._h = None
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """Source tree + sink terms uploaded to the current GPU."""
+
+    def __init__(self, tree: Tree, snk: Terms):
+        if not torch.cuda.is_available():
+            raise RuntimeError("mhc.Plan needs a GPU (HIP device)")
+        self.tree = tree
+        self.snk = snk
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        check(lib().mhc_plan_create(tree.handle, snk.handle, _stream_ptr(),
+                                    ctypes.byref(h)))
+        self._h = h
+        self._destroy = lib().mhc_plan_destroy
+
+    @property
+    def n_src(self):
+        return len(self.tree.terms)
+
+    @property
+    def n_snk(self):
+        return len(self.snk)
+
+    @property
+    def M(self):
+        return self.snk.M
+
+    def fallback_count(self) -> int:
+        v = ctypes.c_int64()
+        check(lib().mhc_plan_status(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._destroy(h)
+            self._h = None
+
+
+def _check_dev(x: torch.Tensor, dtype, shape, name, device):
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {x.dtype}")
+    if tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(x.shape)}")
+    if x.device != device:
+        raise ValueError(f"{name} must be on {device}, got {x.device}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def contract_into(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch.Tensor,
+                  C: torch.Tensor, method: str = "tree", A: torch.Tensor | None = None,
+                  pair_det: torch.Tensor | None = None) -> None:
+    """Enqueue the contraction on torch's current stream, writing C (and A,
+    pair_det if given).  All tensors live on the plan's device."""
+    T = S.shape[0]
+    dev = plan.device
+    _check_dev(S, torch.complex128, (T, plan.M, plan.M), "S", dev)
+    _check_dev(w_src, torch.float64, (plan.n_src,), "w_src", dev)
+    _check_dev(w_snk, torch.float64, (plan.n_snk,), "w_snk", dev)
+    _check_dev(C, torch.complex128, (T,), "C", dev)
+    if A is not None:
+        _check_dev(A, torch.float64, (T,), "A", dev)
+    if pair_det is not None:
+        _check_dev(pair_det, torch.complex128, (T, plan.n_src, plan.n_snk), "pair_det", dev)
+    check(lib().mhc_contract(
+        plan._h, METHODS[method], T, ctypes.c_void_p(S.data_ptr()),
+        ctypes.c_void_p(w_src.data_ptr()), ctypes.c_void_p(w_snk.data_ptr()),
+        ctypes.c_void_p(C.data_ptr()),
+        ctypes.c_void_p(A.data_ptr() if A is not None else 0),
+        ctypes.c_void_p(pair_det.data_ptr() if pair_det is not None else 0),
+        _stream_ptr()))
+
+
+def contract(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch.Tensor,
+             method: str = "tree", with_scale: bool = False, with_pairs: bool = False):
+    """C(t) for every slice (complex128 [T] on the plan's device).  With
+    with_scale / with_pairs also returns A(t) and every pair determinant."""
+    T = S.shape[0]
+    C = torch.empty(T, dtype=torch.complex128, device=plan.device)
+    A = torch.empty(T, dtype=torch.float64, device=plan.device) if with_scale else None
+    P = (torch.empty((T, plan.n_src, plan.n_snk), dtype=torch.complex128, device=plan.device)
+         if with_pairs else None)
+    contract_into(plan, S, w_src, w_snk, C, method, A, P)
+    if not (with_scale or with_pairs):
+        return C
+    out = [C]
+    if with_scale:
+        out.append(A)
+    if with_pairs:
+        out.append(P)
+    return tuple(out)

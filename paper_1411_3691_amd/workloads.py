@@ -73,6 +73,7 @@ def make_propagator(rng, T: int, M: int, decay: float = 0.0,
 def make_plain_terms(rng, n_terms: int, M: int, nf) -> np.ndarray:
     """int32 [n_terms][sum(nf)]: per flavour, nf[f] distinct indices of
     [0, M) in the order drawn."""
+    # (duplicates are possible; the caller decides whether that matters)
     out = np.empty((n_terms, int(sum(nf))), dtype=np.int32)
     for i in range(n_terms):
         parts = [rng.choice(M, size=n, replace=False) for n in nf]
@@ -106,10 +107,15 @@ def make_tree_terms(rng, n_terms: int, M: int, nf, branching: int,
         terms.append(tt)
         return True
 
+    failed_roots = 0
     while len(terms) < n_terms:
         root = np.concatenate([rng.choice(M, size=n, replace=False)
                                for n in nf]).astype(np.int64)
         if not add(root):
+            failed_roots += 1
+            if failed_roots > 1000:
+                raise ValueError(f"cannot draw {n_terms} distinct terms "
+                                 f"from M={M}, nf={tuple(nf)}")
             continue
         d = int(rng.integers(1, depth + 1))
         frontier = [root]

@@ -1,0 +1,234 @@
+"""GPU parity: the HIP kernels behind the C ABI against the CPU oracle.
+
+Tolerances (per pair and per slice):
+* a pair determinant d_ij(t) whose flavour blocks all have 1-norm condition
+  number kappa_1 <= 1e4 must match the oracle to 1e-11 relative; a pair with
+  a worse-conditioned block is held to |delta| <= 4 n eps kappa_1 |d| (two
+  backward-stable eliminations of the same matrix differ by about that);
+* C(t) must match to 1e-9 * A(t), A(t) = sum_ij |w_i w_j d_ij(t)|.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import contract as oc
+from paper_1411_3691_amd import mhc
+from paper_1411_3691_amd import workloads as W
+
+import oracle_pool
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def setup(w, policy="R2"):
+    src = mhc.Terms(w.src, w.nf, w.M)
+    snk = mhc.Terms(w.snk, w.nf, w.M)
+    tree = mhc.Tree(src, policy)
+    plan = mhc.Plan(tree, snk)
+    dev = plan.device
+    S = torch.from_numpy(w.S).to(dev)
+    ws = torch.from_numpy(np.ascontiguousarray(w.w_src)).to(dev)
+    wk = torch.from_numpy(np.ascontiguousarray(w.w_snk)).to(dev)
+    return plan, tree, S, ws, wk
+
+
+def run(plan, S, ws, wk, method, pairs=True):
+    """(C, A, pair dets or None) as numpy arrays."""
+    out = mhc.contract(plan, S, ws, wk, method, with_scale=True, with_pairs=pairs)
+    torch.cuda.synchronize()
+    out = tuple(x.cpu().numpy() for x in out)
+    return out if pairs else out + (None,)
+
+
+def check_pairs(w, P, t, i, j):
+    want = oc.pair_dets(w.S, w.src, w.snk, w.nf, t, i, j)
+    got = P[t, i, j]
+    kap = oc.pair_condition(w.S, w.src, w.snk, w.nf, t, i, j)
+    n = max(w.nf)
+    err = np.abs(got - want)
+    well = kap <= 1e4
+    # exactly singular blocks (kappa = inf) are checked through C(t) only
+    with np.errstate(invalid="ignore"):
+        bound = np.where(well, 1e-11 * np.abs(want), 4 * n * EPS * kap * np.abs(want))
+    bound = np.where(np.isfinite(kap), bound, np.inf)
+    bad = ~(err <= bound)
+    assert not bad.any(), (
+        f"{bad.sum()} of {bad.size} pairs out of tolerance; worst rel "
+        f"{(err / np.abs(want))[bad].max():.3e}")
+    return int(well.sum()), int((~well).sum())
+
+
+def all_pairs(w):
+    t, i, j = np.meshgrid(np.arange(w.T), np.arange(len(w.src)), np.arange(len(w.snk)),
+                          indexing="ij")
+    return t.ravel(), i.ravel(), j.ravel()
+
+
+def check_C(C, A, Cw, Aw):
+    assert np.all(np.abs(C - Cw) <= 1e-9 * Aw), np.max(np.abs(C - Cw) / Aw)
+    np.testing.assert_allclose(A, Aw, rtol=1e-9)
+
+
+@pytest.mark.parametrize("method", ["plain", "tree"])
+def test_tiny_all_pairs(method):
+    # 1 slice, 12 x 12 propagator, 2 flavours of 3 quarks, 64 x 64 terms
+    w = W.workload("tiny")
+    plan, tree, S, ws, wk = setup(w)
+    C, A, P = run(plan, S, ws, wk, method)
+    check_pairs(w, P, *all_pairs(w))
+    Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+    check_C(C, A, Cw, Aw)
+
+
+@pytest.mark.parametrize("method", ["plain", "tree"])
+@pytest.mark.parametrize("policy", ["R2", "R1"])
+def test_mid_shape_small(method, policy):
+    # 2 x 6 quarks, 48 indices, 3 slices, 300 x 200 tree terms (200 sinks =
+    # 3 full blocks of 64 and a ragged tail of 8)
+    w = W.workload("mid", T=3, n_src=300, n_snk=200)
+    plan, tree, S, ws, wk = setup(w, policy)
+    C, A, P = run(plan, S, ws, wk, method)
+    check_pairs(w, P, *all_pairs(w))
+    Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+    check_C(C, A, Cw, Aw)
+
+
+def test_methods_agree_and_fast_path_matches_diagnostic_path():
+    w = W.workload("mid", T=4, n_src=700, n_snk=130)
+    plan, tree, S, ws, wk = setup(w)
+    Cp, Ap, _ = run(plan, S, ws, wk, "plain", pairs=False)
+    Ct, At, _ = run(plan, S, ws, wk, "tree", pairs=False)
+    assert np.all(np.abs(Cp - Ct) <= 2e-9 * Ap)
+    for method, Cref in (("plain", Cp), ("tree", Ct)):
+        C = mhc.contract(plan, S, ws, wk, method)          # no A, no pairs
+        torch.cuda.synchronize()
+        C = C.cpu().numpy()
+        assert np.all(np.abs(C - Cref) <= 1e-12 * Ap)
+
+
+@pytest.mark.parametrize("method", ["plain", "tree"])
+def test_full_mid_in_bench_configuration(method):
+    # 32 slices, 48 x 48 propagators, 2 x 6 quarks, 2000 x 2000 terms: the
+    # benchmark's launch (no A, no pair output); slices 0 and 31 checked
+    # against the oracle, every slice against the other method
+    w = W.workload("mid")
+    plan, tree, S, ws, wk = setup(w)
+    C = mhc.contract(plan, S, ws, wk, method)
+    other = mhc.contract(plan, S, ws, wk, "tree" if method == "plain" else "plain",
+                         with_scale=True)
+    torch.cuda.synchronize()
+    C = C.cpu().numpy()
+    Co, Ao = (x.cpu().numpy() for x in other)
+    assert np.all(np.abs(C - Co) <= 2e-9 * Ao)
+    slices = [0, 31]
+    Cw, Aw = oracle_pool.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk, slices)
+    assert np.all(np.abs(C[slices] - Cw) <= 1e-9 * Aw), np.abs(C[slices] - Cw) / Aw
+    # sampled pair determinants from the diagnostic launch of the same plan
+    _, _, P = run(plan, S, ws, wk, method)
+    rng = np.random.default_rng(5)
+    idx = W.random_pairs(rng, w.T, len(w.src), len(w.snk), 20000)
+    check_pairs(w, P, idx[:, 0], idx[:, 1], idx[:, 2])
+
+
+def test_repeatable_bitwise():
+    w = W.workload("mid", T=2, n_src=400, n_snk=300)
+    plan, tree, S, ws, wk = setup(w)
+    for method in ("plain", "tree"):
+        a = mhc.contract(plan, S, ws, wk, method).cpu().numpy()
+        b = mhc.contract(plan, S, ws, wk, method).cpu().numpy()
+        assert a.tobytes() == b.tobytes()
+
+
+@pytest.mark.parametrize("nf,M,n_src,n_snk", [
+    ((2, 2), 8, 150, 70), ((8, 8), 24, 150, 70), ((5,), 16, 150, 70),
+    ((4, 4, 4), 20, 150, 70), ((1, 1), 6, 30, 30), ((7, 7), 30, 150, 70), ((3,), 4, 4, 4)])
+def test_block_sizes_and_flavour_counts(nf, M, n_src, n_snk):
+    w = W.workload("mid", T=2, M=M, nf=nf, n_src=n_src, n_snk=n_snk, branching=4, depth=3)
+    plan, tree, S, ws, wk = setup(w)
+    for method in ("plain", "tree"):
+        C, A, P = run(plan, S, ws, wk, method)
+        check_pairs(w, P, *all_pairs(w))
+        Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+        check_C(C, A, Cw, Aw)
+
+
+@pytest.mark.parametrize("n_src,n_snk", [(1, 1), (1, 64), (64, 1), (5, 65), (33, 128)])
+def test_small_and_ragged_term_counts(n_src, n_snk):
+    w = W.workload("mid", T=2, n_src=n_src, n_snk=n_snk)
+    plan, tree, S, ws, wk = setup(w)
+    for method in ("plain", "tree"):
+        C, A, P = run(plan, S, ws, wk, method)
+        check_pairs(w, P, *all_pairs(w))
+        Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+        check_C(C, A, Cw, Aw)
+
+
+def test_singular_dominators_take_the_direct_route():
+    # A zero row of S makes every block containing that source index exactly
+    # singular (an exactly zero pivot).  Dominators with such a block have
+    # no inverse; their children that replace the index are regular and must
+    # come out right (direct LU), and the plan counts them.
+    w = W.workload("mid", T=2, M=12, n_src=300, n_snk=100, branching=6, depth=3)
+    w.S[:, 5, :] = 0
+    plan, tree, S, ws, wk = setup(w)
+    for method in ("plain", "tree"):
+        C, A, P = run(plan, S, ws, wk, method)
+        check_pairs(w, P, *all_pairs(w))
+        Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+        check_C(C, A, Cw, Aw)
+    assert plan.fallback_count() > 0
+
+
+def test_near_singular_dominators_stay_accurate():
+    # Two equal rows of S: blocks holding both indices are singular up to
+    # rounding, so the dominator's factors carry a pivot of rounding size;
+    # the rank-1 updates of its regular children stay backward stable.
+    w = W.workload("mid", T=2, M=12, n_src=300, n_snk=100, branching=6, depth=3)
+    w.S[:, 5, :] = w.S[:, 3, :]
+    plan, tree, S, ws, wk = setup(w)
+    for method in ("plain", "tree"):
+        C, A, P = run(plan, S, ws, wk, method)
+        check_pairs(w, P, *all_pairs(w))
+        Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+        check_C(C, A, Cw, Aw)
+
+
+def test_star_and_no_edge_trees():
+    base = W.workload("mid", T=1, n_src=1, n_snk=80)
+    root = base.src[0]
+    # a star: every child changes one slot of the root
+    kids = [root.copy()]
+    for slot in range(len(root)):
+        for c in range(48):
+            f0 = 0 if slot < 6 else 6
+            if c in root[f0:f0 + 6]:
+                continue
+            k = root.copy()
+            k[slot] = c
+            kids.append(k)
+            if len(kids) % 7 == 0:
+                break
+    star = np.array(kids, dtype=np.int32)
+    rng = np.random.default_rng(3)
+    for src in (star, W.make_plain_terms(rng, 90, 48, (6, 6))):
+        w = W.Workload("edge", base.S, src, base.snk, rng.standard_normal(len(src)),
+                       base.w_snk, base.nf, base.cfg)
+        plan, tree, S, ws, wk = setup(w)
+        for method in ("plain", "tree"):
+            C, A, P = run(plan, S, ws, wk, method)
+            check_pairs(w, P, *all_pairs(w))
+            Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+            check_C(C, A, Cw, Aw)
+
+
+def test_decaying_slices_keep_relative_accuracy():
+    # |S_t| ~ exp(-0.5 t): at t = 31 the pair determinants are ~1e-80 of
+    # those at t = 0; the tolerance scales with A(t), so each slice is
+    # checked on its own scale.
+    w = W.workload("mid", n_src=120, n_snk=64)
+    plan, tree, S, ws, wk = setup(w)
+    for method in ("plain", "tree"):
+        C, A, P = run(plan, S, ws, wk, method, pairs=False)
+        Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk, slices=[0, 15, 31])
+        check_C(C[[0, 15, 31]], A[[0, 15, 31]], Cw, Aw)
