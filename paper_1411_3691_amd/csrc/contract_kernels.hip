@@ -79,11 +79,55 @@ __device__ __forceinline__ void gather(const char* lds, const uint32_t (&rowoff)
     }
 }
 
+// In the lanes of `mask` only: a <- b and b <- t (t holds a's old value),
+// for one complex element (two doubles).  The exec mask is narrowed and
+// restored inside one straight-line block, so the compiler sees plain tied
+// register operands and no branch.
+__device__ __forceinline__ void masked_exchange(uint64_t mask, double& ar, double& ai,
+                                                double& br, double& bi, double tr,
+                                                double ti) {
+  uint64_t sv;
+  asm("s_and_saveexec_b64 %[sv], %[mask]\n\t"
+      "v_mov_b64 %[ar], %[br]\n\t"
+      "v_mov_b64 %[ai], %[bi]\n\t"
+      "v_mov_b64 %[br], %[tr]\n\t"
+      "v_mov_b64 %[bi], %[ti]\n\t"
+      "s_mov_b64 exec, %[sv]"
+      // early-clobber: the outputs are written before tr/ti are read, so
+      // no input may share a register with them
+      : [ar] "+&v"(ar), [ai] "+&v"(ai), [br] "+&v"(br), [bi] "+&v"(bi), [sv] "=&s"(sv)
+      : [tr] "v"(tr), [ti] "v"(ti), [mask] "s"(mask)
+      : "scc");  // s_and_saveexec_b64 writes SCC
+}
+
+__device__ __forceinline__ void masked_exchange_i32(uint64_t mask, int& a, int& b, int t) {
+  uint64_t sv;
+  asm("s_and_saveexec_b64 %[sv], %[mask]\n\t"
+      "v_mov_b32 %[a], %[b]\n\t"
+      "v_mov_b32 %[b], %[t]\n\t"
+      "s_mov_b64 exec, %[sv]"
+      : [a] "+&v"(a), [b] "+&v"(b), [sv] "=&s"(sv)
+      : [t] "v"(t), [mask] "s"(mask)
+      : "scc");
+}
+
+// |Re| + |Im| with the row's rank packed into the three lowest mantissa
+// bits, so that one max over rows yields the pivot magnitude and row, the
+// lowest row winning among equal magnitudes (magnitudes that differ only
+// in those bits count as equal).
+__device__ __forceinline__ double pivot_key(double re, double im, int m) {
+  const double mag = fabs(re) + fabs(im);
+  const uint32_t lo = (__double2loint(mag) & ~7u) | (uint32_t)(7 - m);
+  return __hiloint2double(__double2hiint(mag), (int)lo);
+}
+
 // Gaussian elimination with partial pivoting in registers (pivot = largest
-// |Re| + |Im| of the remaining column, lowest row on ties).  Row exchanges
-// are done with selects because the pivot row differs from lane to lane.
-// KEEP: store the multipliers (L, unit diagonal), swap them with their rows
-// (so that P G = L U), replace U_kk by 1/U_kk once it has entered the
+// |Re| + |Im| of the remaining column, lowest row on ties).  Each lane holds
+// its own matrix and the pivot row differs from lane to lane: row k is
+// saved, then for every candidate row m the lanes that chose m copy row m
+// into row k and the saved row into row m.
+// KEEP: store the multipliers (L, unit diagonal), exchange them with their
+// rows (so that P G = L U), replace U_kk by 1/U_kk once it has entered the
 // determinant, and keep the permutation (perm[m] = original row now in
 // position m).  Returns det = sgn(P) prod U_kk and whether some pivot was
 // exactly zero.
@@ -91,6 +135,8 @@ template <int N, bool KEEP>
 __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
                                    double& dre, double& dim, int (&perm)[N],
                                    bool& zero_pivot) {
+  static_assert(N <= 8, "row rank is packed into 3 bits");
+  constexpr int J0 = 0;
   double sre = 1.0, sim = 0.0;
   bool neg = false;
   zero_pivot = false;
@@ -100,42 +146,38 @@ __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    double best = fabs(gr[k][k]) + fabs(gi[k][k]);
-    int p = k;
+    double key = pivot_key(gr[k][k], gi[k][k], k);
 #pragma unroll
-    for (int m = k + 1; m < N; ++m) {
-      const double mag = fabs(gr[m][k]) + fabs(gi[m][k]);
-      const bool gt = mag > best;
-      best = gt ? mag : best;
-      p = gt ? m : p;
-    }
+    for (int m = k + 1; m < N; ++m) key = fmax(key, pivot_key(gr[m][k], gi[m][k], m));
+    const int p = 7 - (int)(__double2loint(key) & 7u);
+    if (k + 1 < N) {
+      double tr[N], ti[N];
+      int tp = 0;
 #pragma unroll
-    for (int m = k + 1; m < N; ++m) {
-      const bool s = (p == m);
-#pragma unroll
-      for (int j = (KEEP ? 0 : k); j < N; ++j) {
-        const double ar = gr[k][j], br = gr[m][j];
-        const double ai = gi[k][j], bi = gi[m][j];
-        gr[k][j] = s ? br : ar;
-        gr[m][j] = s ? ar : br;
-        gi[k][j] = s ? bi : ai;
-        gi[m][j] = s ? ai : bi;
+      for (int j = (KEEP ? J0 : k); j < N; ++j) {
+        tr[j] = gr[k][j];
+        ti[j] = gi[k][j];
       }
-      if (KEEP) {
-        const int a = perm[k], b = perm[m];
-        perm[k] = s ? b : a;
-        perm[m] = s ? a : b;
+      if (KEEP) tp = perm[k];
+#pragma unroll
+      for (int m = k + 1; m < N; ++m) {
+        const uint64_t mask = __builtin_amdgcn_ballot_w64(p == m);
+#pragma unroll
+        for (int j = (KEEP ? J0 : k); j < N; ++j)
+          masked_exchange(mask, gr[k][j], gi[k][j], gr[m][j], gi[m][j], tr[j], ti[j]);
+        if (KEEP) masked_exchange_i32(mask, perm[k], perm[m], tp);
       }
     }
     neg = neg != (p != k);
     const double pr = gr[k][k], pi = gi[k][k];
-    zero_pivot = zero_pivot || (best == 0.0);
+    const double mag = fabs(pr) + fabs(pi);
+    zero_pivot = zero_pivot || (mag == 0.0);
     const double t = sre * pr - sim * pi;
     sim = sre * pi + sim * pr;
     sre = t;
     if (KEEP || k + 1 < N) {
       double vr, vi;
-      cinv(pr, pi, best, vr, vi);
+      cinv(pr, pi, mag, vr, vi);
       if (KEEP) {
         gr[k][k] = vr;
         gi[k][k] = vi;
@@ -306,15 +348,18 @@ __global__ __launch_bounds__(kBlock, 2) void contract_kernel(ContractArgs a) {
       int perm[N];
       double dre, dim;
       bool zero;
-      gather<N>(lds, ro, co, gr, gi);
       // groups of this flavour form a contiguous run [g, g_f_end)
       int g_f_end = g;
       if (TREE) {
         while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
       }
       double accre = 0.0, accim = 0.0;
-      if (TREE && g_f_end > g) {
-        lu<N, true>(gr, gi, dre, dim, perm, zero);
+      gather<N>(lds, ro, co, gr, gi);
+      // The tree keeps the multipliers for every dominator block: nearly
+      // every dominator has groups in every flavour, and a single
+      // factorisation path keeps the register allocation within budget.
+      lu<N, TREE>(gr, gi, dre, dim, perm, zero);
+      if (TREE) {
         double sre = 0.0, sim = 0.0;
         for (int gg = g; gg < g_f_end; ++gg) {
           const int r = uniform(p.grp_fr[gg] & 0xff);
@@ -347,12 +392,11 @@ __global__ __launch_bounds__(kBlock, 2) void contract_kernel(ContractArgs a) {
         accim = zero ? 0.0 : dre * sim + dim * sre;
         if (zero) {
           ++nbad;
-          fbad = f;
+          fbad = g_f_end > g ? f : -2;   // -2: singular, but nothing to redo
         }
-      } else {
-        lu<N, false>(gr, gi, dre, dim, perm, zero);
-        if (zero) ++nbad;   // det is 0: no fallback work, but X excludes it
-        if (zero) fbad = -2;
+      } else if (zero) {
+        ++nbad;
+        fbad = -2;
       }
       g = g_f_end;
       // Q <- Q * D + acc * P ;  P <- P * D

@@ -16,6 +16,7 @@ from paper_1411_3691_amd import mhc
 from paper_1411_3691_amd import workloads as W
 
 import oracle_pool
+from parity_util import all_pairs, check_C, check_pairs
 
 pytestmark = pytest.mark.gpu
 EPS = np.finfo(np.float64).eps
@@ -39,35 +40,6 @@ def run(plan, S, ws, wk, method, pairs=True):
     torch.cuda.synchronize()
     out = tuple(x.cpu().numpy() for x in out)
     return out if pairs else out + (None,)
-
-
-def check_pairs(w, P, t, i, j):
-    want = oc.pair_dets(w.S, w.src, w.snk, w.nf, t, i, j)
-    got = P[t, i, j]
-    kap = oc.pair_condition(w.S, w.src, w.snk, w.nf, t, i, j)
-    n = max(w.nf)
-    err = np.abs(got - want)
-    well = kap <= 1e4
-    # exactly singular blocks (kappa = inf) are checked through C(t) only
-    with np.errstate(invalid="ignore"):
-        bound = np.where(well, 1e-11 * np.abs(want), 4 * n * EPS * kap * np.abs(want))
-    bound = np.where(np.isfinite(kap), bound, np.inf)
-    bad = ~(err <= bound)
-    assert not bad.any(), (
-        f"{bad.sum()} of {bad.size} pairs out of tolerance; worst rel "
-        f"{(err / np.abs(want))[bad].max():.3e}")
-    return int(well.sum()), int((~well).sum())
-
-
-def all_pairs(w):
-    t, i, j = np.meshgrid(np.arange(w.T), np.arange(len(w.src)), np.arange(len(w.snk)),
-                          indexing="ij")
-    return t.ravel(), i.ravel(), j.ravel()
-
-
-def check_C(C, A, Cw, Aw):
-    assert np.all(np.abs(C - Cw) <= 1e-9 * Aw), np.max(np.abs(C - Cw) / Aw)
-    np.testing.assert_allclose(A, Aw, rtol=1e-9)
 
 
 @pytest.mark.parametrize("method", ["plain", "tree"])

@@ -346,3 +346,20 @@ def test_sibling_sharing_and_multilinearity():
     tot = sum(w[k] * od.det_gepp(np.vstack([G[:r], rows[k][None], G[r + 1:]]))
               for k in range(5))
     assert tot == pytest.approx(od.det_gepp(Gw), rel=1e-11)
+
+
+def test_adjugate_norm_against_cofactors():
+    # the tolerance helper's ||adj G||_1 against cofactors by brute force,
+    # for a regular and an exactly singular matrix
+    rng = np.random.default_rng(31)
+    for singular in (False, True):
+        G = rand_c(rng, (4, 4))
+        if singular:
+            G[2] = G[0]
+        C = np.zeros((4, 4), complex)
+        for r in range(4):
+            for c in range(4):
+                minor = np.delete(np.delete(G, r, 0), c, 1)
+                C[r, c] = (-1) ** (r + c) * qi_to_complex(od.det_exact(minor))
+        want = np.abs(C.T).sum(axis=0).max()
+        assert oc.adjugate_1norm(G[None])[0] == pytest.approx(want, rel=1e-12)
