@@ -16,10 +16,13 @@ computes, in float64 (complex128) or exact rational arithmetic:
                   exact (``math.fsum``) summation.
 * ``tree``     -- the source-term graph and the greedy dominating set
                   (Sec. 3), in the readings listed in the design notes.
+* ``grad``     -- derivatives of the correlator with respect to the weights
+                  and the propagator (Jacobi's formula with cofactors).
 
 It shares no code with the GPU path.  Every function is pinned by tests in
-``tests/test_oracle.py`` and ``tests/test_oracle_tree.py`` against values the
+``tests/test_oracle.py``, ``tests/test_oracle_tree.py`` and
+``tests/test_oracle_grad.py`` against values the
 mathematics fixes (exact rational results, closed forms, brute force, an
 independent library routine).
 """
-from . import det, contract, tree  # noqa: F401
+from . import det, contract, tree, grad  # noqa: F401

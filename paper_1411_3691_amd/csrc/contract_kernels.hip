@@ -45,22 +45,21 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
-// 1 / (pr + i pi) with the magnitude mag = |pr| + |pi| > 0 known.  Scaled by
-// a power of two so that |pr|^2 + |pi|^2 can neither overflow nor
-// underflow; returns 0 for a zero pivot.
+// 1 / (pr + i pi) with the magnitude mag = |pr| + |pi| known.  Scaled by a
+// power of two so that |pr|^2 + |pi|^2 can neither overflow nor underflow
+// (it then lies in [1/8, 1)); a zero pivot gives 0 (the clamp of the scaled
+// norm keeps 0 * (1/norm) finite).
 __device__ __forceinline__ void cinv(double pr, double pi, double mag,
                                      double& vr, double& vi) {
-  int e = __builtin_amdgcn_frexp_exp(mag);
-  double a = __builtin_amdgcn_ldexp(pr, -e);
-  double b = __builtin_amdgcn_ldexp(pi, -e);
-  double d = a * a + b * b;  // in [1/8, 1)
+  const int e = __builtin_amdgcn_frexp_exp(mag);
+  const double a = __builtin_amdgcn_ldexp(pr, -e);
+  const double b = __builtin_amdgcn_ldexp(pi, -e);
+  const double d = fmax(a * a + b * b, 0.125);
   double r = __builtin_amdgcn_rcp(d);
   r = fma(r, fma(-d, r, 1.0), r);
   r = fma(r, fma(-d, r, 1.0), r);
   vr = __builtin_amdgcn_ldexp(a * r, -e);
   vi = __builtin_amdgcn_ldexp(-b * r, -e);
-  vr = mag > 0.0 ? vr : 0.0;
-  vi = mag > 0.0 ? vi : 0.0;
 }
 
 // G[m][n] = S_t[row_m][col_n]: rowoff/coloff are byte offsets into the LDS
@@ -79,35 +78,61 @@ __device__ __forceinline__ void gather(const char* lds, const uint32_t (&rowoff)
     }
 }
 
-// In the lanes of `mask` only: a <- b and b <- t (t holds a's old value),
-// for one complex element (two doubles).  The exec mask is narrowed and
-// restored inside one straight-line block, so the compiler sees plain tied
-// register operands and no branch.
-__device__ __forceinline__ void masked_exchange(uint64_t mask, double& ar, double& ai,
-                                                double& br, double& bi, double tr,
-                                                double ti) {
+// Row exchange in the lanes of `mask` only: a <- b, b <- t, where t holds
+// a's old value.  The EXEC mask is narrowed and restored inside one
+// straight-line asm block, so the compiler sees no branch.  Every operand,
+// t included, is a read-write register operand: outputs never share a
+// register, so no value the block reads can sit in a register it has
+// already written.  The block writes SCC.
+__device__ __forceinline__ void masked_exchange1(uint64_t mask, double (&a)[2], double (&b)[2],
+                                                 double (&t)[2]) {
   uint64_t sv;
   asm("s_and_saveexec_b64 %[sv], %[mask]\n\t"
-      "v_mov_b64 %[ar], %[br]\n\t"
-      "v_mov_b64 %[ai], %[bi]\n\t"
-      "v_mov_b64 %[br], %[tr]\n\t"
-      "v_mov_b64 %[bi], %[ti]\n\t"
+      "v_mov_b64 %[a0], %[b0]\n\t"
+      "v_mov_b64 %[a1], %[b1]\n\t"
+      "v_mov_b64 %[b0], %[t0]\n\t"
+      "v_mov_b64 %[b1], %[t1]\n\t"
       "s_mov_b64 exec, %[sv]"
-      // early-clobber: the outputs are written before tr/ti are read, so
-      // no input may share a register with them
-      : [ar] "+&v"(ar), [ai] "+&v"(ai), [br] "+&v"(br), [bi] "+&v"(bi), [sv] "=&s"(sv)
-      : [tr] "v"(tr), [ti] "v"(ti), [mask] "s"(mask)
-      : "scc");  // s_and_saveexec_b64 writes SCC
+      : [a0] "+v"(a[0]), [a1] "+v"(a[1]), [b0] "+v"(b[0]), [b1] "+v"(b[1]),
+        [t0] "+v"(t[0]), [t1] "+v"(t[1]), [sv] "=&s"(sv)
+      : [mask] "s"(mask)
+      : "scc");
 }
 
-__device__ __forceinline__ void masked_exchange_i32(uint64_t mask, int& a, int& b, int t) {
+// The same for three complex elements (q = 2 * element + re/im).
+__device__ __forceinline__ void masked_exchange3(uint64_t mask, double (&a)[6], double (&b)[6],
+                                                 double (&t)[6]) {
+  uint64_t sv;
+  asm("s_and_saveexec_b64 %[sv], %[mask]\n\t"
+      "v_mov_b64 %[a0], %[b0]\n\t"
+      "v_mov_b64 %[a1], %[b1]\n\t"
+      "v_mov_b64 %[a2], %[b2]\n\t"
+      "v_mov_b64 %[a3], %[b3]\n\t"
+      "v_mov_b64 %[a4], %[b4]\n\t"
+      "v_mov_b64 %[a5], %[b5]\n\t"
+      "v_mov_b64 %[b0], %[t0]\n\t"
+      "v_mov_b64 %[b1], %[t1]\n\t"
+      "v_mov_b64 %[b2], %[t2]\n\t"
+      "v_mov_b64 %[b3], %[t3]\n\t"
+      "v_mov_b64 %[b4], %[t4]\n\t"
+      "v_mov_b64 %[b5], %[t5]\n\t"
+      "s_mov_b64 exec, %[sv]"
+      : [a0] "+v"(a[0]), [a1] "+v"(a[1]), [a2] "+v"(a[2]), [a3] "+v"(a[3]), [a4] "+v"(a[4]),
+        [a5] "+v"(a[5]), [b0] "+v"(b[0]), [b1] "+v"(b[1]), [b2] "+v"(b[2]), [b3] "+v"(b[3]),
+        [b4] "+v"(b[4]), [b5] "+v"(b[5]), [t0] "+v"(t[0]), [t1] "+v"(t[1]), [t2] "+v"(t[2]),
+        [t3] "+v"(t[3]), [t4] "+v"(t[4]), [t5] "+v"(t[5]), [sv] "=&s"(sv)
+      : [mask] "s"(mask)
+      : "scc");
+}
+
+__device__ __forceinline__ void masked_exchange_i32(uint64_t mask, int& a, int& b, int& t) {
   uint64_t sv;
   asm("s_and_saveexec_b64 %[sv], %[mask]\n\t"
       "v_mov_b32 %[a], %[b]\n\t"
       "v_mov_b32 %[b], %[t]\n\t"
       "s_mov_b64 exec, %[sv]"
-      : [a] "+&v"(a), [b] "+&v"(b), [sv] "=&s"(sv)
-      : [t] "v"(t), [mask] "s"(mask)
+      : [a] "+v"(a), [b] "+v"(b), [t] "+v"(t), [sv] "=&s"(sv)
+      : [mask] "s"(mask)
       : "scc");
 }
 
@@ -124,7 +149,7 @@ __device__ __forceinline__ double pivot_key(double re, double im, int m) {
 // Gaussian elimination with partial pivoting in registers (pivot = largest
 // |Re| + |Im| of the remaining column, lowest row on ties).  Each lane holds
 // its own matrix and the pivot row differs from lane to lane: row k is
-// saved, then for every candidate row m the lanes that chose m copy row m
+// saved, then for every candidate row m the lanes that chose m move row m
 // into row k and the saved row into row m.
 // KEEP: store the multipliers (L, unit diagonal), exchange them with their
 // rows (so that P G = L U), replace U_kk by 1/U_kk once it has entered the
@@ -136,7 +161,6 @@ __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
                                    double& dre, double& dim, int (&perm)[N],
                                    bool& zero_pivot) {
   static_assert(N <= 8, "row rank is packed into 3 bits");
-  constexpr int J0 = 0;
   double sre = 1.0, sim = 0.0;
   bool neg = false;
   zero_pivot = false;
@@ -150,11 +174,15 @@ __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
 #pragma unroll
     for (int m = k + 1; m < N; ++m) key = fmax(key, pivot_key(gr[m][k], gi[m][k], m));
     const int p = 7 - (int)(__double2loint(key) & 7u);
+    // Row exchange k <-> p: row k's old value is saved, then for each
+    // candidate row m the lanes that chose m move row m into row k and the
+    // saved row into row m (the L part too when the factors are kept).
     if (k + 1 < N) {
+      const int jb = KEEP ? 0 : k;
       double tr[N], ti[N];
       int tp = 0;
 #pragma unroll
-      for (int j = (KEEP ? J0 : k); j < N; ++j) {
+      for (int j = jb; j < N; ++j) {
         tr[j] = gr[k][j];
         ti[j] = gi[k][j];
       }
@@ -163,8 +191,37 @@ __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
       for (int m = k + 1; m < N; ++m) {
         const uint64_t mask = __builtin_amdgcn_ballot_w64(p == m);
 #pragma unroll
-        for (int j = (KEEP ? J0 : k); j < N; ++j)
-          masked_exchange(mask, gr[k][j], gi[k][j], gr[m][j], gi[m][j], tr[j], ti[j]);
+        for (int j = jb; j < N; j += 3) {
+          if (j + 2 < N) {
+            double a6[6] = {gr[k][j], gi[k][j], gr[k][j + 1], gi[k][j + 1], gr[k][j + 2], gi[k][j + 2]};
+            double b6[6] = {gr[m][j], gi[m][j], gr[m][j + 1], gi[m][j + 1], gr[m][j + 2], gi[m][j + 2]};
+            double t6[6] = {tr[j], ti[j], tr[j + 1], ti[j + 1], tr[j + 2], ti[j + 2]};
+            masked_exchange3(mask, a6, b6, t6);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              gr[k][j + q] = a6[2 * q];
+              gi[k][j + q] = a6[2 * q + 1];
+              gr[m][j + q] = b6[2 * q];
+              gi[m][j + q] = b6[2 * q + 1];
+              tr[j + q] = t6[2 * q];
+              ti[j + q] = t6[2 * q + 1];
+            }
+          } else {
+#pragma unroll
+            for (int jj = j; jj < N; ++jj) {
+              double a2[2] = {gr[k][jj], gi[k][jj]};
+              double b2[2] = {gr[m][jj], gi[m][jj]};
+              double t2[2] = {tr[jj], ti[jj]};
+              masked_exchange1(mask, a2, b2, t2);
+              gr[k][jj] = a2[0];
+              gi[k][jj] = a2[1];
+              gr[m][jj] = b2[0];
+              gi[m][jj] = b2[1];
+              tr[jj] = t2[0];
+              ti[jj] = t2[1];
+            }
+          }
+        }
         if (KEEP) masked_exchange_i32(mask, perm[k], perm[m], tp);
       }
     }

@@ -2,11 +2,12 @@
 kernels (CPU only: hipcc cross-compiles).
 
 The pivoted LU exchanges rows with inline-asm blocks that narrow EXEC and
-move registers.  Two properties must hold in every such block:
+move registers (row k <- row m, row m <- saved row k).  Properties that
+must hold in every such block:
 * no scalar-condition (SCC) value of the surrounding code is live across it
   (the block writes SCC);
-* no register read by the block was already written earlier in the same
-  block (its outputs are early-clobber).
+* no register the block reads was already written earlier in the block;
+* the block restores EXEC from the value it saved.
 """
 import os
 import re
@@ -63,10 +64,14 @@ def vregs(tok):
 def test_exchange_blocks_read_nothing_they_already_wrote(asm):
     n = 0
     for i, _, body in asm_blocks(asm):
+        moves = [ins for ins in body if ins.startswith("v_mov")]
+        if not moves:
+            continue
+        assert body[0].startswith("s_and_saveexec_b64") and body[-1].startswith("s_mov_b64 exec")
+        saved = body[0].split(None, 1)[1].split(",")[0].strip()
+        assert body[-1].split(",")[1].strip() == saved, f"line {i}: {body}"
         written = set()
-        for ins in body:
-            if not ins.startswith("v_mov"):
-                continue
+        for ins in moves:
             dst, src = [p.strip() for p in ins.split(None, 1)[1].split(",")[:2]]
             assert not (vregs(src) & written), f"line {i}: {body}"
             written |= vregs(dst)
