@@ -137,7 +137,8 @@ void mhc_plan_destroy(mhc_plan* plan);
  *   A         double [T] or NULL: A(t) = sum_ij |w_i w'_j d_ij(t)| (output;
  *             the scale the result's accuracy is judged against)
  *   pair_det  complex128 [T][n_src][n_snk] or NULL: every d_ij(t) =
- *             prod_f det G_f^(ij)(t) (output; a test hook)
+ *             prod_f det G_f^(ij)(t) (output; a test hook, at most 4
+ *             flavour blocks)
  * T >= 1.  method is MHC_PLAIN_LU or MHC_UPDATE_TREE; both return the same
  * quantities within floating-point rounding.  Every pointer must stay valid
  * until the stream has run the work. */
@@ -146,11 +147,35 @@ mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
                         const double* w_snk, void* C, double* A,
                         void* pair_det, void* stream);
 
-/* Number of (pair, flavour, child) determinants that the update path took
- * by direct LU because the dominator's factorisation had an exactly zero
- * pivot, summed over all completed calls on this plan.  Synchronises the
- * device first. */
-mhc_status mhc_plan_status(mhc_plan* plan, int64_t* n_fallback);
+/* Adjoint of mhc_contract (both methods compute the same C; the adjoint
+ * recomputes every pair's LU).  For an incoming gradient gC of a real loss
+ * (PyTorch's convention for complex tensors):
+ *   gS[t][p][q] = gC[t] * conj(dC(t)/dS_t[p][q])      complex128 [T][M][M]
+ *   g_wsrc[i]   = Re(sum_t gC[t] * conj(dC(t)/dw_i))   double [n_src]
+ *   g_wsnk[j]   = Re(sum_t gC[t] * conj(dC(t)/dw'_j))  double [n_snk]
+ * dC/dS follows from Jacobi's formula (d det G / dG[m][n] = det(G)
+ * (G^-1)[n][m]) applied to every flavour block of every pair (Sec. 1
+ * definitions); dC/dw from bilinearity.  Inputs as for mhc_contract; gC is
+ * complex128 [T].  Any output pointer may be NULL (not written).  At most 4
+ * flavour blocks; S_t and its gradient must fit in LDS together
+ * (2 * M * M * 16 bytes).  A flavour block with an exactly zero pivot
+ * contributes nothing to gS and is counted (mhc_plan_status).  Device
+ * scratch is allocated on the plan at the first call (and grown when T
+ * grows). */
+mhc_status mhc_contract_backward(mhc_plan* plan, int32_t T, const void* S,
+                                 const double* w_src, const double* w_snk,
+                                 const void* gC, void* gS, double* g_wsrc,
+                                 double* g_wsnk, void* stream);
+
+/* Counters summed over all completed calls on this plan (either pointer may
+ * be NULL); synchronises the device first.
+ *   n_fallback       children whose flavour block the update path took by
+ *                    direct LU because the dominator block had an exactly
+ *                    zero pivot (no inverse);
+ *   n_singular_grad  (pair, flavour) blocks with an exactly zero pivot that
+ *                    the adjoint skipped. */
+mhc_status mhc_plan_status(mhc_plan* plan, int64_t* n_fallback,
+                           int64_t* n_singular_grad);
 
 #ifdef __cplusplus
 }

@@ -79,8 +79,24 @@ def dC_dw_entries(S, src, snk, nf, w_src, w_snk, src_idx=(), snk_idx=()):
     return gs, gk
 
 
-def dC_dS_entry(S, src, snk, nf, w_src, w_snk, t, p, q) -> complex:
-    """dC(t)/dS_t[p][q] for one propagator entry."""
+def cofactor_at(G, m, n) -> np.ndarray:
+    """The single cofactor (-1)^(m+n) det(minor(m, n)) of each matrix of a
+    batch G [B][k][k] at per-matrix positions m[B], n[B]."""
+    G = np.asarray(G)
+    B, k, _ = G.shape
+    if k == 1:
+        return np.ones(B, dtype=np.complex128)
+    base = np.arange(k - 1)
+    rows = base[None, :] + (base[None, :] >= np.asarray(m)[:, None])   # skip row m
+    cols = base[None, :] + (base[None, :] >= np.asarray(n)[:, None])   # skip column n
+    minor = G[np.arange(B)[:, None, None], rows[:, :, None], cols[:, None, :]]
+    sign = np.where((np.asarray(m) + np.asarray(n)) % 2 == 0, 1.0, -1.0)
+    return sign * det_gepp(minor)
+
+
+def dC_dS_entry(S, src, snk, nf, w_src, w_snk, t, p, q, with_scale=False):
+    """dC(t)/dS_t[p][q] for one propagator entry (and, with with_scale, the
+    sum of the magnitudes of its terms)."""
     S = np.asarray(S)
     src = np.asarray(src)
     snk = np.asarray(snk)
@@ -99,7 +115,7 @@ def dC_dS_entry(S, src, snk, nf, w_src, w_snk, t, p, q) -> complex:
         m = np.argmax(a[ii] == p, axis=1)          # row of p in block f
         n = np.argmax(b[jj] == q, axis=1)          # column of q in block f
         G = S[t][a[ii][:, :, None], b[jj][:, None, :]]
-        cof = cofactors(G)[np.arange(len(ii)), m, n]
+        cof = cofactor_at(G, m, n)
         other = np.ones(len(ii), dtype=np.complex128)
         for g in range(len(nf)):
             if g == f:
@@ -109,9 +125,12 @@ def dC_dS_entry(S, src, snk, nf, w_src, w_snk, t, p, q) -> complex:
             other = other * det_gepp(S[t][ag[:, :, None], bg[:, None, :]])
         terms.append(np.asarray(w_src)[ii] * np.asarray(w_snk)[jj] * other * cof)
     if not terms:
-        return 0j
+        return (0j, 0.0) if with_scale else 0j
     z = np.concatenate(terms)
-    return complex(math.fsum(z.real.tolist()), math.fsum(z.imag.tolist()))
+    val = complex(math.fsum(z.real.tolist()), math.fsum(z.imag.tolist()))
+    if with_scale:
+        return val, math.fsum(np.abs(z).tolist())
+    return val
 
 
 def dC_dS(S, src, snk, nf, w_src, w_snk) -> np.ndarray:
@@ -144,4 +163,4 @@ def vjp(S, src, snk, nf, w_src, w_snk, gC, entries=None):
     return gS, g_wsrc, g_wsnk
 
 
-__all__ = ["cofactors", "dC_dw", "dC_dS_entry", "dC_dS", "vjp", "pair_dets"]
+__all__ = ["cofactors", "cofactor_at", "dC_dw", "dC_dw_entries", "dC_dS_entry", "dC_dS", "vjp"]

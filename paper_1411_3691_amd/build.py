@@ -27,7 +27,7 @@ COMMON = [
     "-Wall", "-Wno-unused-result",
 ]
 
-SOURCES = ["mhc_host.cpp", "mhc_plan.hip", "contract_kernels.hip"]
+SOURCES = ["mhc_host.cpp", "mhc_plan.hip", "contract_kernels.hip", "adjoint_kernels.hip"]
 
 
 def _compile(src: str) -> str:

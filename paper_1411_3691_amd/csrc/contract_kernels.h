@@ -45,3 +45,28 @@ hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag,
 
 }  // namespace kern
 }  // namespace mhc
+
+namespace mhc {
+namespace kern {
+
+struct AdjointArgs {
+  PlanView plan;
+  const double2* S;               // [T][M][M]
+  const double* w_src;            // [n_src]
+  const double* w_snk;            // [n_snk]
+  const double2* gC;              // [T] incoming gradient
+  double2* part_gS;               // [T][n_sblk][M*M] workgroup partials
+  double* part_wsrc;              // [T][n_src][n_sblk]
+  double* part_wsnk;              // [T][n_snk_pad]
+  unsigned long long* singular;   // blocks with an exactly zero pivot (skipped)
+  int T, n_sblk;
+};
+
+// Enqueues the adjoint of the plain contraction and the fixed-order
+// reductions into gS [T][M][M], g_wsrc [n_src], g_wsnk [n_snk] (any output
+// may be null).
+hipError_t launch_adjoint(const AdjointArgs& a, int n, double2* gS, double* g_wsrc,
+                          double* g_wsnk, hipStream_t s);
+
+}  // namespace kern
+}  // namespace mhc

@@ -1,0 +1,274 @@
+// Device building blocks shared by the forward and adjoint kernels:
+// LDS gather of a flavour block, pivoted complex LU in registers (one matrix
+// per lane), unit-vector solves, reciprocal, wave reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mhc {
+namespace kern {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// 1 / (pr + i pi) with the magnitude mag = |pr| + |pi| known.  Scaled by a
+// power of two so that |pr|^2 + |pi|^2 can neither overflow nor underflow
+// (it then lies in [1/8, 1)); a zero pivot gives 0 (the clamp of the scaled
+// norm keeps 0 * (1/norm) finite).
+__device__ __forceinline__ void cinv(double pr, double pi, double mag,
+                                     double& vr, double& vi) {
+  const int e = __builtin_amdgcn_frexp_exp(mag);
+  const double a = __builtin_amdgcn_ldexp(pr, -e);
+  const double b = __builtin_amdgcn_ldexp(pi, -e);
+  const double d = fmax(a * a + b * b, 0.125);
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  vr = __builtin_amdgcn_ldexp(a * r, -e);
+  vi = __builtin_amdgcn_ldexp(-b * r, -e);
+}
+
+// G[m][n] = S_t[row_m][col_n]: rowoff/coloff are byte offsets into the LDS
+// copy of S_t (row * M * 16 and col * 16).
+template <int N>
+__device__ __forceinline__ void gather(const char* lds, const uint32_t (&rowoff)[N],
+                                       const uint32_t (&coloff)[N],
+                                       double (&gr)[N][N], double (&gi)[N][N]) {
+#pragma unroll
+  for (int m = 0; m < N; ++m)
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      const double2 v = *reinterpret_cast<const double2*>(lds + rowoff[m] + coloff[n]);
+      gr[m][n] = v.x;
+      gi[m][n] = v.y;
+    }
+}
+
+// Row exchange in the lanes of `mask` only: a <- b, b <- t, where t holds
+// a's old value.  The EXEC mask is narrowed and restored inside one
+// straight-line asm block, so the compiler sees no branch.  Every operand,
+// t included, is a read-write register operand: outputs never share a
+// register, so no value the block reads can sit in a register it has
+// already written.  The block writes SCC.
+__device__ __forceinline__ void masked_exchange1(uint64_t mask, double (&a)[2], double (&b)[2],
+                                                 double (&t)[2]) {
+  uint64_t sv;
+  asm("s_and_saveexec_b64 %[sv], %[mask]\n\t"
+      "v_mov_b64 %[a0], %[b0]\n\t"
+      "v_mov_b64 %[a1], %[b1]\n\t"
+      "v_mov_b64 %[b0], %[t0]\n\t"
+      "v_mov_b64 %[b1], %[t1]\n\t"
+      "s_mov_b64 exec, %[sv]"
+      : [a0] "+v"(a[0]), [a1] "+v"(a[1]), [b0] "+v"(b[0]), [b1] "+v"(b[1]),
+        [t0] "+v"(t[0]), [t1] "+v"(t[1]), [sv] "=&s"(sv)
+      : [mask] "s"(mask)
+      : "scc");
+}
+
+// The same for three complex elements (q = 2 * element + re/im).
+__device__ __forceinline__ void masked_exchange3(uint64_t mask, double (&a)[6], double (&b)[6],
+                                                 double (&t)[6]) {
+  uint64_t sv;
+  asm("s_and_saveexec_b64 %[sv], %[mask]\n\t"
+      "v_mov_b64 %[a0], %[b0]\n\t"
+      "v_mov_b64 %[a1], %[b1]\n\t"
+      "v_mov_b64 %[a2], %[b2]\n\t"
+      "v_mov_b64 %[a3], %[b3]\n\t"
+      "v_mov_b64 %[a4], %[b4]\n\t"
+      "v_mov_b64 %[a5], %[b5]\n\t"
+      "v_mov_b64 %[b0], %[t0]\n\t"
+      "v_mov_b64 %[b1], %[t1]\n\t"
+      "v_mov_b64 %[b2], %[t2]\n\t"
+      "v_mov_b64 %[b3], %[t3]\n\t"
+      "v_mov_b64 %[b4], %[t4]\n\t"
+      "v_mov_b64 %[b5], %[t5]\n\t"
+      "s_mov_b64 exec, %[sv]"
+      : [a0] "+v"(a[0]), [a1] "+v"(a[1]), [a2] "+v"(a[2]), [a3] "+v"(a[3]), [a4] "+v"(a[4]),
+        [a5] "+v"(a[5]), [b0] "+v"(b[0]), [b1] "+v"(b[1]), [b2] "+v"(b[2]), [b3] "+v"(b[3]),
+        [b4] "+v"(b[4]), [b5] "+v"(b[5]), [t0] "+v"(t[0]), [t1] "+v"(t[1]), [t2] "+v"(t[2]),
+        [t3] "+v"(t[3]), [t4] "+v"(t[4]), [t5] "+v"(t[5]), [sv] "=&s"(sv)
+      : [mask] "s"(mask)
+      : "scc");
+}
+
+__device__ __forceinline__ void masked_exchange_i32(uint64_t mask, int& a, int& b, int& t) {
+  uint64_t sv;
+  asm("s_and_saveexec_b64 %[sv], %[mask]\n\t"
+      "v_mov_b32 %[a], %[b]\n\t"
+      "v_mov_b32 %[b], %[t]\n\t"
+      "s_mov_b64 exec, %[sv]"
+      : [a] "+v"(a), [b] "+v"(b), [t] "+v"(t), [sv] "=&s"(sv)
+      : [mask] "s"(mask)
+      : "scc");
+}
+
+// |Re| + |Im| with the row's rank packed into the three lowest mantissa
+// bits, so that one max over rows yields the pivot magnitude and row, the
+// lowest row winning among equal magnitudes (magnitudes that differ only
+// in those bits count as equal).
+__device__ __forceinline__ double pivot_key(double re, double im, int m) {
+  const double mag = fabs(re) + fabs(im);
+  const uint32_t lo = (__double2loint(mag) & ~7u) | (uint32_t)(7 - m);
+  return __hiloint2double(__double2hiint(mag), (int)lo);
+}
+
+// Gaussian elimination with partial pivoting in registers (pivot = largest
+// |Re| + |Im| of the remaining column, lowest row on ties).  Each lane holds
+// its own matrix and the pivot row differs from lane to lane: row k is
+// saved, then for every candidate row m the lanes that chose m move row m
+// into row k and the saved row into row m.
+// KEEP: store the multipliers (L, unit diagonal), exchange them with their
+// rows (so that P G = L U), replace U_kk by 1/U_kk once it has entered the
+// determinant, and keep the permutation (perm[m] = original row now in
+// position m).  Returns det = sgn(P) prod U_kk and whether some pivot was
+// exactly zero.
+template <int N, bool KEEP>
+__device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
+                                   double& dre, double& dim, int (&perm)[N],
+                                   bool& zero_pivot) {
+  static_assert(N <= 8, "row rank is packed into 3 bits");
+  double sre = 1.0, sim = 0.0;
+  bool neg = false;
+  zero_pivot = false;
+  if (KEEP) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) perm[m] = m;
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double key = pivot_key(gr[k][k], gi[k][k], k);
+#pragma unroll
+    for (int m = k + 1; m < N; ++m) key = fmax(key, pivot_key(gr[m][k], gi[m][k], m));
+    const int p = 7 - (int)(__double2loint(key) & 7u);
+    // Row exchange k <-> p: row k's old value is saved, then for each
+    // candidate row m the lanes that chose m move row m into row k and the
+    // saved row into row m (the L part too when the factors are kept).
+    if (k + 1 < N) {
+      const int jb = KEEP ? 0 : k;
+      double tr[N], ti[N];
+      int tp = 0;
+#pragma unroll
+      for (int j = jb; j < N; ++j) {
+        tr[j] = gr[k][j];
+        ti[j] = gi[k][j];
+      }
+      if (KEEP) tp = perm[k];
+#pragma unroll
+      for (int m = k + 1; m < N; ++m) {
+        const uint64_t mask = __builtin_amdgcn_ballot_w64(p == m);
+#pragma unroll
+        for (int j = jb; j < N; j += 3) {
+          if (j + 2 < N) {
+            double a6[6] = {gr[k][j], gi[k][j], gr[k][j + 1], gi[k][j + 1], gr[k][j + 2], gi[k][j + 2]};
+            double b6[6] = {gr[m][j], gi[m][j], gr[m][j + 1], gi[m][j + 1], gr[m][j + 2], gi[m][j + 2]};
+            double t6[6] = {tr[j], ti[j], tr[j + 1], ti[j + 1], tr[j + 2], ti[j + 2]};
+            masked_exchange3(mask, a6, b6, t6);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              gr[k][j + q] = a6[2 * q];
+              gi[k][j + q] = a6[2 * q + 1];
+              gr[m][j + q] = b6[2 * q];
+              gi[m][j + q] = b6[2 * q + 1];
+              tr[j + q] = t6[2 * q];
+              ti[j + q] = t6[2 * q + 1];
+            }
+          } else {
+#pragma unroll
+            for (int jj = j; jj < N; ++jj) {
+              double a2[2] = {gr[k][jj], gi[k][jj]};
+              double b2[2] = {gr[m][jj], gi[m][jj]};
+              double t2[2] = {tr[jj], ti[jj]};
+              masked_exchange1(mask, a2, b2, t2);
+              gr[k][jj] = a2[0];
+              gi[k][jj] = a2[1];
+              gr[m][jj] = b2[0];
+              gi[m][jj] = b2[1];
+              tr[jj] = t2[0];
+              ti[jj] = t2[1];
+            }
+          }
+        }
+        if (KEEP) masked_exchange_i32(mask, perm[k], perm[m], tp);
+      }
+    }
+    neg = neg != (p != k);
+    const double pr = gr[k][k], pi = gi[k][k];
+    const double mag = fabs(pr) + fabs(pi);
+    zero_pivot = zero_pivot || (mag == 0.0);
+    const double t = sre * pr - sim * pi;
+    sim = sre * pi + sim * pr;
+    sre = t;
+    if (KEEP || k + 1 < N) {
+      double vr, vi;
+      cinv(pr, pi, mag, vr, vi);
+      if (KEEP) {
+        gr[k][k] = vr;
+        gi[k][k] = vi;
+      }
+#pragma unroll
+      for (int m = k + 1; m < N; ++m) {
+        const double lr = gr[m][k] * vr - gi[m][k] * vi;
+        const double li = gr[m][k] * vi + gi[m][k] * vr;
+        if (KEEP) {
+          gr[m][k] = lr;
+          gi[m][k] = li;
+        }
+#pragma unroll
+        for (int j = k + 1; j < N; ++j) {
+          gr[m][j] = gr[m][j] - lr * gr[k][j] + li * gi[k][j];
+          gi[m][j] = gi[m][j] - lr * gi[k][j] - li * gr[k][j];
+        }
+      }
+    }
+  }
+  dre = neg ? -sre : sre;
+  dim = neg ? -sim : sim;
+}
+
+// x = G^-1 e_r from the factors of lu<N, true>: solve L y = P e_r (P e_r is
+// the unit vector at the position q with perm[q] == r), then U x = y (the
+// diagonal of the factors holds 1/U_mm).
+template <int N>
+__device__ __forceinline__ void solve_unit(const double (&gr)[N][N],
+                                           const double (&gi)[N][N],
+                                           const int (&perm)[N], int r,
+                                           double (&xr)[N], double (&xi)[N]) {
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    double br = perm[m] == r ? 1.0 : 0.0, bi = 0.0;
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      br = br - gr[m][j] * xr[j] + gi[m][j] * xi[j];
+      bi = bi - gr[m][j] * xi[j] - gi[m][j] * xr[j];
+    }
+    xr[m] = br;
+    xi[m] = bi;
+  }
+#pragma unroll
+  for (int m = N - 1; m >= 0; --m) {
+    double br = xr[m], bi = xi[m];
+#pragma unroll
+    for (int j = m + 1; j < N; ++j) {
+      br = br - gr[m][j] * xr[j] + gi[m][j] * xi[j];
+      bi = bi - gr[m][j] * xi[j] - gi[m][j] * xr[j];
+    }
+    xr[m] = br * gr[m][m] - bi * gi[m][m];
+    xi[m] = br * gi[m][m] + bi * gr[m][m];
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int uniform(int v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+}  // namespace kern
+}  // namespace mhc

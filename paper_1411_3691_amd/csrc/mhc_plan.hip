@@ -29,6 +29,10 @@ struct mhc_plan {
   double* partial = nullptr;           // workgroup partials
   size_t partial_cap = 0;              // in doubles
   unsigned long long* fallback = nullptr;
+  unsigned long long* singular = nullptr;
+  // adjoint scratch (grown on demand)
+  void* adj_scratch = nullptr;
+  size_t adj_cap = 0;
 };
 
 namespace {
@@ -138,7 +142,7 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   const size_t o_child_term = append(img, child_term);
   const size_t o_src_rowoff = append(img, src_rowoff);
   const size_t o_snk_coloff = append(img, snk_coloff);
-  const size_t o_fallback = append(img, std::vector<unsigned long long>(1, 0ull));
+  const size_t o_fallback = append(img, std::vector<unsigned long long>(2, 0ull));
 
   e = hipMalloc(&pl->dev_tables, img.size());
   if (e != hipSuccess) {
@@ -175,6 +179,7 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   v.src_rowoff = reinterpret_cast<const uint32_t*>(base + o_src_rowoff);
   v.snk_coloff = reinterpret_cast<const uint32_t*>(base + o_snk_coloff);
   pl->fallback = reinterpret_cast<unsigned long long*>(base + o_fallback);
+  pl->singular = pl->fallback + 1;
   *out = pl;
   return MHC_OK;
 }
@@ -186,6 +191,7 @@ void mhc_plan_destroy(mhc_plan* pl) {
   hipSetDevice(pl->device);
   hipDeviceSynchronize();
   if (pl->partial) hipFree(pl->partial);
+  if (pl->adj_scratch) hipFree(pl->adj_scratch);
   if (pl->dev_tables) hipFree(pl->dev_tables);
   hipSetDevice(cur);
   delete pl;
@@ -207,6 +213,9 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   if (cur != pl->device)
     return fail(MHC_E_DEVICE, "mhc_contract: current device differs from "
                               "the plan's device");
+  if (pair_det && pl->F > 4)
+    return fail(MHC_E_UNSUPPORTED,
+                "mhc_contract: pair_det output supports at most 4 flavour blocks");
   const bool tree = method == MHC_UPDATE_TREE;
   const bool diag = A != nullptr || pair_det != nullptr;
   const int rowsets = tree ? pl->n_dom : pl->n_src;
@@ -250,14 +259,76 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   return MHC_OK;
 }
 
-mhc_status mhc_plan_status(mhc_plan* pl, int64_t* n_fallback) {
-  if (!pl || !n_fallback) return fail(MHC_E_ARG, "mhc_plan_status: NULL");
+mhc_status mhc_contract_backward(mhc_plan* pl, int32_t T, const void* S,
+                                 const double* w_src, const double* w_snk,
+                                 const void* gC, void* gS, double* g_wsrc,
+                                 double* g_wsnk, void* stream) {
+  if (!pl) return fail(MHC_E_ARG, "mhc_contract_backward: NULL plan");
+  if (!S || !w_src || !w_snk || !gC)
+    return fail(MHC_E_ARG, "mhc_contract_backward: NULL input buffer");
+  if (T < 1 || T > 65535)
+    return fail(MHC_E_ARG, "mhc_contract_backward: T outside [1, 65535]");
+  if (pl->F > 4)
+    return fail(MHC_E_UNSUPPORTED,
+                "mhc_contract_backward: more than 4 flavour blocks");
+  if ((size_t)2 * pl->M * pl->M * 16 > 160 * 1024 - 4096)
+    return fail(MHC_E_UNSUPPORTED,
+                "mhc_contract_backward: S_t and its gradient must fit in LDS");
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "mhc_contract_backward/hipGetDevice");
+  if (cur != pl->device)
+    return fail(MHC_E_DEVICE, "mhc_contract_backward: current device differs "
+                              "from the plan's device");
+  const int n_sblk = pl->n_snk_pad / kSinkBlock;
+  const size_t MM = (size_t)pl->M * pl->M;
+  const size_t b_gS = (size_t)T * n_sblk * MM * 16;
+  const size_t b_src = ((size_t)T * pl->n_src * n_sblk * 8 + 255) & ~size_t(255);
+  const size_t b_snk = (size_t)T * pl->n_snk_pad * 8;
+  const size_t need = b_gS + b_src + b_snk;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (need > pl->adj_cap) {
+    if (pl->adj_scratch) {
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_fail(e, "mhc_contract_backward/sync");
+      hipFree(pl->adj_scratch);
+      pl->adj_scratch = nullptr;
+      pl->adj_cap = 0;
+    }
+    e = hipMalloc(&pl->adj_scratch, need);
+    if (e != hipSuccess)
+      return fail(MHC_E_OOM, std::string("mhc_contract_backward/hipMalloc: ") +
+                                 hipGetErrorString(e));
+    pl->adj_cap = need;
+  }
+  char* base = static_cast<char*>(pl->adj_scratch);
+  mhc::kern::AdjointArgs a{};
+  a.plan = pl->view;
+  a.S = static_cast<const double2*>(S);
+  a.w_src = w_src;
+  a.w_snk = w_snk;
+  a.gC = static_cast<const double2*>(gC);
+  a.part_gS = reinterpret_cast<double2*>(base);
+  a.part_wsrc = reinterpret_cast<double*>(base + b_gS);
+  a.part_wsnk = reinterpret_cast<double*>(base + b_gS + b_src);
+  a.singular = pl->singular;
+  a.T = T;
+  a.n_sblk = n_sblk;
+  e = mhc::kern::launch_adjoint(a, pl->n, static_cast<double2*>(gS), g_wsrc, g_wsnk, s);
+  if (e != hipSuccess) return hip_fail(e, "mhc_contract_backward/launch");
+  return MHC_OK;
+}
+
+mhc_status mhc_plan_status(mhc_plan* pl, int64_t* n_fallback,
+                           int64_t* n_singular_grad) {
+  if (!pl) return fail(MHC_E_ARG, "mhc_plan_status: NULL plan");
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "mhc_plan_status/sync");
-  unsigned long long v = 0;
-  e = hipMemcpy(&v, pl->fallback, sizeof(v), hipMemcpyDeviceToHost);
+  unsigned long long v[2] = {0, 0};
+  e = hipMemcpy(v, pl->fallback, sizeof(v), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "mhc_plan_status/copy");
-  *n_fallback = (int64_t)v;
+  if (n_fallback) *n_fallback = (int64_t)v[0];
+  if (n_singular_grad) *n_singular_grad = (int64_t)v[1];
   return MHC_OK;
 }
 

@@ -128,10 +128,14 @@ class Plan:
     def M(self):
         return self.snk.M
 
+    def status(self) -> dict:
+        """Counters over completed calls (synchronises the device)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().mhc_plan_status(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return dict(n_fallback=int(a.value), n_singular_grad=int(b.value))
+
     def fallback_count(self) -> int:
-        v = ctypes.c_int64()
-        check(lib().mhc_plan_status(self._h, ctypes.byref(v)))
-        return int(v.value)
+        return self.status()["n_fallback"]
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -193,3 +197,46 @@ def contract(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch.Tens
     if with_pairs:
         out.append(P)
     return tuple(out)
+
+
+def contract_backward(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch.Tensor,
+                      gC: torch.Tensor):
+    """(grad_S, grad_w_src, grad_w_snk) of a real loss whose gradient with
+    respect to C is gC (PyTorch's complex convention), from the library's
+    adjoint kernels."""
+    T = S.shape[0]
+    dev = plan.device
+    _check_dev(S, torch.complex128, (T, plan.M, plan.M), "S", dev)
+    _check_dev(w_src, torch.float64, (plan.n_src,), "w_src", dev)
+    _check_dev(w_snk, torch.float64, (plan.n_snk,), "w_snk", dev)
+    gC = gC.to(device=dev, dtype=torch.complex128).contiguous()
+    _check_dev(gC, torch.complex128, (T,), "gC", dev)
+    gS = torch.empty_like(S)
+    g_src = torch.empty_like(w_src)
+    g_snk = torch.empty_like(w_snk)
+    check(lib().mhc_contract_backward(
+        plan._h, T, ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(w_src.data_ptr()),
+        ctypes.c_void_p(w_snk.data_ptr()), ctypes.c_void_p(gC.data_ptr()),
+        ctypes.c_void_p(gS.data_ptr()), ctypes.c_void_p(g_src.data_ptr()),
+        ctypes.c_void_p(g_snk.data_ptr()), _stream_ptr()))
+    return gS, g_src, g_snk
+
+
+class Contract(torch.autograd.Function):
+    """C = Contract.apply(plan, S, w_src, w_snk, method): differentiable in S
+    and both weight arrays; the backward pass is the library's adjoint."""
+
+    @staticmethod
+    def forward(ctx, plan, S, w_src, w_snk, method="tree"):
+        ctx.plan = plan
+        ctx.save_for_backward(S, w_src, w_snk)
+        return contract(plan, S.contiguous(), w_src.contiguous(), w_snk.contiguous(), method)
+
+    @staticmethod
+    def backward(ctx, gC):
+        S, w_src, w_snk = ctx.saved_tensors
+        gS, g_src, g_snk = contract_backward(ctx.plan, S.contiguous(), w_src.contiguous(),
+                                             w_snk.contiguous(), gC)
+        return (None, gS if ctx.needs_input_grad[1] else None,
+                g_src if ctx.needs_input_grad[2] else None,
+                g_snk if ctx.needs_input_grad[3] else None, None)

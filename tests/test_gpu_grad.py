@@ -1,0 +1,126 @@
+"""GPU adjoint: the library's backward kernels against PyTorch's gradcheck,
+the CPU gradient oracle and complex central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import grad as og
+from paper_1411_3691_amd import mhc
+from paper_1411_3691_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def setup(w):
+    src = mhc.Terms(w.src, w.nf, w.M)
+    snk = mhc.Terms(w.snk, w.nf, w.M)
+    plan = mhc.Plan(mhc.Tree(src), snk)
+    dev = plan.device
+    return (plan, torch.from_numpy(w.S).to(dev), torch.from_numpy(w.w_src).to(dev),
+            torch.from_numpy(w.w_snk).to(dev))
+
+
+def test_gradcheck_tiny():
+    # 1 slice, 7 quark indices, two flavours of 2, 5 x 4 terms
+    w = W.workload("mid", T=1, M=7, nf=(2, 2), n_src=5, n_snk=4, branching=2, depth=2)
+    plan, S, ws, wk = setup(w)
+    S.requires_grad_(True)
+    ws.requires_grad_(True)
+    wk.requires_grad_(True)
+    # grad S is summed with LDS atomics across waves: repeatable up to
+    # rounding, hence a small nondeterminism tolerance
+    for method in ("plain", "tree"):
+        assert torch.autograd.gradcheck(
+            lambda s, a, b: mhc.Contract.apply(plan, s, a, b, method), (S, ws, wk),
+            eps=1e-6, atol=1e-7, rtol=1e-5, nondet_tol=1e-12)
+
+
+def test_full_gradient_against_oracle_small():
+    # every entry of grad S and both weight gradients, 2 slices, blocks of 3,
+    # 20 x 70 terms (one full sink block of 64 and a ragged one)
+    w = W.workload("mid", T=2, M=10, nf=(3, 3), n_src=20, n_snk=70, branching=3, depth=2)
+    plan, S, ws, wk = setup(w)
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal(w.T) + 1j * rng.standard_normal(w.T)
+    gS, gws, gwk = mhc.contract_backward(plan, S, ws, wk, torch.from_numpy(g))
+    torch.cuda.synchronize()
+    gS, gws, gwk = gS.cpu().numpy(), gws.cpu().numpy(), gwk.cpu().numpy()
+    oS, ows, owk = og.vjp(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk, g)
+    scale = np.abs(oS).max()
+    np.testing.assert_allclose(gS, oS, atol=1e-11 * scale, rtol=1e-9)
+    np.testing.assert_allclose(gws, ows, atol=1e-11 * np.abs(ows).max(), rtol=1e-9)
+    np.testing.assert_allclose(gwk, owk, atol=1e-11 * np.abs(owk).max(), rtol=1e-9)
+    assert plan.status()["n_singular_grad"] == 0
+
+
+def test_grad_workload_sampled_entries():
+    # 32 slices, M = 48, blocks of 6, 2000 x 2000 tree terms: 16 random
+    # entries of grad S and 16 random weights per side against the oracle
+    # (within 1e-9 of the sum of the magnitudes of each entry's terms) and
+    # against complex central differences of the GPU forward (h = 1e-6)
+    w = W.workload("grad")
+    plan, S, ws, wk = setup(w)
+    rng = np.random.default_rng(9)
+    g = rng.standard_normal(w.T) + 1j * rng.standard_normal(w.T)
+    gS, gws, gwk = mhc.contract_backward(plan, S, ws, wk, torch.from_numpy(g))
+    torch.cuda.synchronize()
+    gS, gws, gwk = gS.cpu().numpy(), gws.cpu().numpy(), gwk.cpu().numpy()
+
+    entries = [(int(rng.integers(w.T)), int(rng.integers(w.M)), int(rng.integers(w.M)))
+               for _ in range(16)]
+    for (t, p, q) in entries:
+        d, sc = og.dC_dS_entry(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk, t, p, q,
+                               with_scale=True)
+        want = g[t] * np.conj(d)
+        assert abs(gS[t, p, q] - want) <= 1e-9 * abs(g[t]) * sc + 1e-300, (t, p, q)
+    isrc = rng.choice(len(w.src), 16, replace=False)
+    isnk = rng.choice(len(w.snk), 16, replace=False)
+    ds, dk = og.dC_dw_entries(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk, isrc, isnk)
+    want_s = np.real(g[:, None] * np.conj(ds)).sum(axis=0)
+    want_k = np.real(g[:, None] * np.conj(dk)).sum(axis=0)
+    np.testing.assert_allclose(gws[isrc], want_s, rtol=1e-9, atol=1e-12 * np.abs(want_s).max())
+    np.testing.assert_allclose(gwk[isnk], want_k, rtol=1e-9, atol=1e-12 * np.abs(want_k).max())
+
+    # finite differences through the GPU forward: for an entry of slice t the
+    # loss is that slice's term Re(conj(g_t) C_t) (the other slices do not
+    # depend on S_t) and the step is 1e-6 of the slice's scale e^{-0.5 t};
+    # for a weight the loss is L = Re(sum_t conj(g_t) C_t)
+    gt = torch.from_numpy(g).to(plan.device)
+
+    def L(S_, ws_, wk_, t=None):
+        C = mhc.contract(plan, S_, ws_, wk_, "tree")
+        z = torch.conj(gt) * C
+        return float(torch.real(z[t] if t is not None else torch.sum(z)).item())
+
+    for (t, p, q) in entries[:8]:
+        h = 1e-6 * float(np.abs(w.S[t]).max())
+        E = torch.zeros_like(S)
+        E[t, p, q] = h
+        fx = (L(S + E, ws, wk, t) - L(S - E, ws, wk, t)) / (2 * h)
+        fy = (L(S + 1j * E, ws, wk, t) - L(S - 1j * E, ws, wk, t)) / (2 * h)
+        ref = abs(gS[t]).max()
+        assert abs(complex(fx, fy) - gS[t, p, q]) <= 1e-5 * ref, (t, p, q)
+    h = 1e-6
+    for i in isrc[:8]:
+        e = torch.zeros_like(ws)
+        e[i] = h
+        fd = (L(S, ws + e, wk) - L(S, ws - e, wk)) / (2 * h)
+        assert fd == pytest.approx(gws[i], rel=1e-5, abs=1e-5 * np.abs(gws).max())
+    for j in isnk[:8]:
+        e = torch.zeros_like(wk)
+        e[j] = h
+        fd = (L(S, ws, wk + e) - L(S, ws, wk - e)) / (2 * h)
+        assert fd == pytest.approx(gwk[j], rel=1e-5, abs=1e-5 * np.abs(gwk).max())
+
+
+def test_backward_repeatable_in_weights():
+    w = W.workload("mid", T=2, n_src=200, n_snk=130)
+    plan, S, ws, wk = setup(w)
+    g = torch.tensor([1.0 - 0.5j, 0.25 + 2j], dtype=torch.complex128)
+    a = mhc.contract_backward(plan, S, ws, wk, g)
+    b = mhc.contract_backward(plan, S, ws, wk, g)
+    torch.cuda.synchronize()
+    assert a[1].cpu().numpy().tobytes() == b[1].cpu().numpy().tobytes()
+    assert a[2].cpu().numpy().tobytes() == b[2].cpu().numpy().tobytes()
+    np.testing.assert_allclose(a[0].cpu().numpy(), b[0].cpu().numpy(), rtol=1e-12,
+                               atol=1e-14 * float(a[0].abs().max()))

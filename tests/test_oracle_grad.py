@@ -101,3 +101,12 @@ def test_vjp_against_finite_differences_of_a_real_loss():
         fx = (L(S + E, ws, wk) - L(S - E, ws, wk)) / (2 * h)
         fy = (L(S + 1j * E, ws, wk) - L(S - 1j * E, ws, wk)) / (2 * h)
         assert complex(fx, fy) == pytest.approx(gS[t, p, q], rel=1e-7, abs=1e-9)
+
+
+def test_single_cofactor_matches_full_table():
+    rng = np.random.default_rng(6)
+    G = rand_c(rng, (20, 5, 5))
+    m = rng.integers(0, 5, 20)
+    n = rng.integers(0, 5, 20)
+    full = og.cofactors(G)
+    np.testing.assert_allclose(og.cofactor_at(G, m, n), full[np.arange(20), m, n], rtol=1e-13)
