@@ -123,8 +123,10 @@ void mhc_tree_destroy(mhc_tree* tree);
 
 /* Device plan: the source tree and the sink terms uploaded once to the
  * current HIP device (Sec. 3: built once and reused across configurations).
- * Both term sets must have the same flavour structure and M.  Enqueues the
- * uploads on `stream`. */
+ * Both term sets must have the same flavour structure and M.  Flavour blocks
+ * may differ in size; the largest must be <= 24, and one slice of S
+ * (M * M * 16 bytes) must fit in 150 KiB (M <= 96); otherwise
+ * MHC_E_UNSUPPORTED.  Enqueues the uploads on `stream` and waits for them. */
 mhc_status mhc_plan_create(const mhc_tree* src_tree, const mhc_terms* snk,
                            void* stream, mhc_plan** out);
 void mhc_plan_destroy(mhc_plan* plan);

@@ -27,7 +27,8 @@ COMMON = [
     "-Wall", "-Wno-unused-result",
 ]
 
-SOURCES = ["mhc_host.cpp", "mhc_plan.hip", "contract_kernels.hip", "adjoint_kernels.hip"]
+SOURCES = ["mhc_host.cpp", "mhc_plan.hip", "contract_kernels.hip", "wide_kernels.hip",
+           "adjoint_kernels.hip"]
 
 
 def _compile(src: str) -> str:

@@ -37,11 +37,25 @@ struct ContractArgs {
   int T, n_items, n_blk_t, n_sblk;
 };
 
-// Enqueues the contraction of all T slices (n = block size of every
-// flavour) and the final reduction into C[T] (and A[T] if non-null).
-// diag selects the kernels that also produce A and pair determinants.
+// Flavour blocks supported by the pair-determinant test hook.
+constexpr int kPairFlavors = 4;
+
+// Enqueues the contraction of all T slices with one matrix per lane (every
+// flavour block of size n <= 8) and the final reduction into C[T] (and A[T]
+// if non-null).  diag selects the kernels that also produce A and pair
+// determinants.  Work items are (row set, block of 64 sinks).
 hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag,
                            double2* C, double* A, hipStream_t s);
+
+// The same with one group of lanes per matrix (one row per lane): blocks of
+// any sizes up to nmax <= 24, different per flavour.  Work items are
+// (row set, block of wide_sinks_per_wave(nmax) sinks).
+hipError_t launch_contract_wide(const ContractArgs& a, int nmax, bool tree, bool diag,
+                                double2* C, double* A, hipStream_t s);
+int wide_sinks_per_wave(int nmax);
+
+// Final fixed-order reduction of the workgroup partials into C (and A).
+hipError_t launch_reduce(const ContractArgs& a, double2* C, double* A, hipStream_t s);
 
 }  // namespace kern
 }  // namespace mhc

@@ -42,9 +42,6 @@
 namespace mhc {
 namespace kern {
 
-// Flavour blocks supported by the pair-determinant test hook.
-constexpr int kPairFlavors = 4;
-
 // Determinant of flavour block f of the pair (row set, sink) with row r
 // replaced by the source row `newrow` (byte offset), by direct LU.
 template <int N>
@@ -345,6 +342,9 @@ template <int N, bool TREE, int MODE>
 static hipError_t launch_one(const ContractArgs& a, hipStream_t s) {
   dim3 grid(a.n_blk_t, a.T);
   size_t lds = (size_t)a.plan.M * a.plan.M * sizeof(double2);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&contract_kernel<N, TREE, MODE>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((contract_kernel<N, TREE, MODE>), grid, dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
@@ -370,6 +370,10 @@ hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag,
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
+  return launch_reduce(a, C, A, s);
+}
+
+hipError_t launch_reduce(const ContractArgs& a, double2* C, double* A, hipStream_t s) {
   hipLaunchKernelGGL(reduce_partials, dim3(a.T), dim3(kBlock), 0, s, a.partial, a.n_blk_t, C, A);
   return hipGetLastError();
 }

@@ -21,7 +21,9 @@ using mhc::fail;
 
 struct mhc_plan {
   int device = 0;
-  int32_t n_src = 0, n_snk = 0, n_snk_pad = 0, M = 0, F = 0, sn = 0, n = 0;
+  int32_t n_src = 0, n_snk = 0, n_snk_pad = 0, M = 0, F = 0, sn = 0;
+  int32_t n = 0;          // largest flavour block
+  bool uniform_n = true;  // every flavour block has size n
   int32_t n_dom = 0, n_groups = 0, n_children = 0;
   std::vector<int32_t> off;
   void* dev_tables = nullptr;          // one allocation for every table
@@ -67,19 +69,18 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
     return fail(MHC_E_SHAPE,
                 "mhc_plan_create: source and sink terms differ in M or in "
                 "their flavour blocks");
-  const int n = src.nf[0];
-  for (int f = 1; f < src.n_flavors; ++f)
-    if (src.nf[f] != n)
-      return fail(MHC_E_UNSUPPORTED,
-                  "mhc_plan_create: flavour blocks of different sizes are not "
-                  "supported by this kernel set");
-  if (n > 8)
+  int nmax = 0;
+  bool uniform_n = true;
+  for (int f = 0; f < src.n_flavors; ++f) {
+    nmax = std::max(nmax, src.nf[f]);
+    uniform_n = uniform_n && src.nf[f] == src.nf[0];
+  }
+  if (nmax > 24)
     return fail(MHC_E_UNSUPPORTED,
-                "mhc_plan_create: flavour blocks larger than 8 are not "
-                "supported by this kernel set");
-  if ((size_t)src.M * src.M * 16 > 64 * 1024)
+                "mhc_plan_create: flavour blocks larger than 24 are not supported");
+  if ((size_t)src.M * src.M * 16 > 150 * 1024)
     return fail(MHC_E_UNSUPPORTED,
-                "mhc_plan_create: M*M*16 bytes must fit in 64 KiB of LDS");
+                "mhc_plan_create: a slice of S (M*M*16 bytes) must fit in 150 KiB of LDS");
 
   mhc_plan* pl = new (std::nothrow) mhc_plan();
   if (!pl) return fail(MHC_E_OOM, "mhc_plan_create: out of host memory");
@@ -94,7 +95,8 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   pl->M = src.M;
   pl->F = src.n_flavors;
   pl->sn = src.sn;
-  pl->n = n;
+  pl->n = nmax;
+  pl->uniform_n = uniform_n;
   pl->off = src.off;
   pl->n_dom = (int32_t)tree->dom_order.size();
   pl->n_groups = (int32_t)tree->grp_f.size();
@@ -218,13 +220,18 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
                 "mhc_contract: pair_det output supports at most 4 flavour blocks");
   const bool tree = method == MHC_UPDATE_TREE;
   const bool diag = A != nullptr || pair_det != nullptr;
+  // one matrix per lane when every block has the same size n <= 8, else one
+  // group of lanes per matrix
+  const bool narrow = pl->uniform_n && pl->n <= 8;
+  const int sinks_per_item = narrow ? kSinkBlock : mhc::kern::wide_sinks_per_wave(pl->n);
+  const int waves_per_block = narrow ? 4 : 8;
   const int rowsets = tree ? pl->n_dom : pl->n_src;
-  const int n_sblk = pl->n_snk_pad / kSinkBlock;
+  const int n_sblk = (pl->n_snk + sinks_per_item - 1) / sinks_per_item;
   const long long n_items = (long long)rowsets * n_sblk;
   if (n_items > 0x7fffffffLL)
     return fail(MHC_E_UNSUPPORTED, "mhc_contract: too many work items");
   int n_blk_t = (kTargetBlocks + T - 1) / T;
-  n_blk_t = (int)std::min<long long>(n_blk_t, (n_items + 3) / 4);
+  n_blk_t = (int)std::min<long long>(n_blk_t, (n_items + waves_per_block - 1) / waves_per_block);
   n_blk_t = std::max(1, n_blk_t);
   const size_t need = (size_t)T * n_blk_t * 3;
   if (need > pl->partial_cap) {
@@ -253,8 +260,12 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   a.n_items = (int)n_items;
   a.n_blk_t = n_blk_t;
   a.n_sblk = n_sblk;
-  e = mhc::kern::launch_contract(a, pl->n, tree, diag, static_cast<double2*>(C),
-                                 A, reinterpret_cast<hipStream_t>(stream));
+  if (narrow)
+    e = mhc::kern::launch_contract(a, pl->n, tree, diag, static_cast<double2*>(C), A,
+                                   reinterpret_cast<hipStream_t>(stream));
+  else
+    e = mhc::kern::launch_contract_wide(a, pl->n, tree, diag, static_cast<double2*>(C), A,
+                                        reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "mhc_contract/launch");
   return MHC_OK;
 }
@@ -271,6 +282,9 @@ mhc_status mhc_contract_backward(mhc_plan* pl, int32_t T, const void* S,
   if (pl->F > 4)
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_contract_backward: more than 4 flavour blocks");
+  if (!pl->uniform_n || pl->n > 8)
+    return fail(MHC_E_UNSUPPORTED,
+                "mhc_contract_backward: flavour blocks must share one size n <= 8");
   if ((size_t)2 * pl->M * pl->M * 16 > 160 * 1024 - 4096)
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_contract_backward: S_t and its gradient must fit in LDS");

@@ -1,0 +1,458 @@
+// Contraction kernels for flavour blocks of any size up to NMAX (gfx950).
+//
+// One group of GROUP lanes (16 or 32) holds one matrix, one row per lane, so
+// a row exchange is a relabelling: no data moves.  Every block of every
+// flavour may have its own size n <= NMAX (lanes m >= n hold no row).
+//
+// Per flavour block of a (row set, sink) pair the group runs Gauss-Jordan
+// elimination with partial pivoting (pivot = largest |Re| + |Im| among the
+// rows not yet used, lowest row on ties) on [G | E], where E holds the unit
+// columns e_r of the rows r that the row set's children change.  Eliminating
+// every other row at every step (not only the rows below) costs nothing
+// extra here -- a lane whose row is done would idle otherwise -- and leaves
+// each row m with one non-zero, its pivot u_m in column c_m, so that
+// x = G^-1 e_r has x[c_m] = E'_m / u_m: no triangular solve is needed.
+// det G = sign(pivot order) * prod_k u_k, the same pivots as GEPP.  A child
+// whose row r is replaced by s has det = det G * (s . x) (matrix determinant
+// lemma, Sec. 2): each lane multiplies s[c_m] by x[c_m] and the group sums.
+//
+// Work decomposition: a wave holds 64 / GROUP sinks of one row set (the
+// tree structure stays wave-uniform); a workgroup stages S_t in LDS and its
+// waves walk a strided share of the slice's items, as in the one-lane-per-
+// matrix kernels.  Reductions are fixed-order.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "contract_kernels.h"
+#include "lu_device.h"
+
+namespace mhc {
+namespace kern {
+
+constexpr int kWideBlock = 512;
+constexpr int kWideWaves = kWideBlock / kWave;
+
+template <int GROUP>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = GROUP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GROUP);
+  return v;
+}
+
+template <int GROUP>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+  for (int o = GROUP / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, GROUP));
+  return v;
+}
+
+// Result of eliminating one flavour block.
+struct GJResult {
+  double dre, dim;   // det G (same value in every lane of the group)
+  bool zero;         // some pivot was exactly zero
+};
+
+// Gauss-Jordan on the group's matrix.  (ar, ai)[c]: this lane's row
+// (columns c < n); (xr, xi)[q]: this lane's entries of the R appended unit
+// columns.  On return, lane m < n holds the reciprocal of its pivot in
+// (ur, ui) and the column it pivoted in (col); its appended entries E'_m
+// then give x[col] = E'_m / u_m for each appended column.
+template <int GROUP, int NMAX>
+__device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai)[NMAX],
+                                                 double (&xr)[NMAX], double (&xi)[NMAX], int R,
+                                                 int n, int m, double& ur, double& ui,
+                                                 int& col) {
+  static_assert(GROUP <= 32, "lane rank is packed into 5 bits");
+  GJResult res{1.0, 0.0, false};
+  bool done = m >= n;
+  bool neg = false;
+  const int gbase = (__lane_id() / GROUP) * GROUP;
+  ur = 0.0;
+  ui = 0.0;
+  col = -1;
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) {
+    if (k >= n) break;
+    // pivot: largest |Re|+|Im| of column k among rows not used yet
+    const double mag = fabs(ar[k]) + fabs(ai[k]);
+    const uint32_t lo = (__double2loint(mag) & ~31u) | (uint32_t)(31 - m);
+    double key = done ? -1.0 : __hiloint2double(__double2hiint(mag), (int)lo);
+    key = group_max<GROUP>(key);
+    // (some row of the group is always unused at step k < n, so the max
+    // carries a rank 0 <= p < GROUP; the mask only keeps the lane in range)
+    const int p = (31 - (int)(__double2loint(key) & 31u)) & (GROUP - 1);
+    // sign: rows below p that are still unused each contribute one
+    // transposition to the pivot permutation
+    const uint64_t open = __builtin_amdgcn_ballot_w64(!done);
+    const uint32_t below = (uint32_t)((open >> gbase) & ((1ull << p) - 1ull));
+    neg = neg != ((__builtin_popcount(below) & 1) != 0);
+    // pivot row, broadcast to the group
+    const int src = gbase + p;
+    const double pr = __shfl(ar[k], src, 64);
+    const double pi = __shfl(ai[k], src, 64);
+    const double pmag = fabs(pr) + fabs(pi);
+    res.zero = res.zero || (pmag == 0.0);
+    const double t = res.dre * pr - res.dim * pi;
+    res.dim = res.dre * pi + res.dim * pr;
+    res.dre = t;
+    double vr, vi;
+    cinv(pr, pi, pmag, vr, vi);
+    const bool me = (m == p);
+    if (me) {
+      ur = vr;
+      ui = vi;
+      col = k;
+      done = true;
+    }
+    // multiplier of this row (0 for the pivot row and empty lanes)
+    double lr = ar[k] * vr - ai[k] * vi;
+    double li = ar[k] * vi + ai[k] * vr;
+    if (me || m >= n) {
+      lr = 0.0;
+      li = 0.0;
+    }
+#pragma unroll
+    for (int c = k + 1; c < NMAX; ++c) {
+      if (c >= n) break;
+      const double br = __shfl(ar[c], src, 64);
+      const double bi = __shfl(ai[c], src, 64);
+      ar[c] = ar[c] - lr * br + li * bi;
+      ai[c] = ai[c] - lr * bi - li * br;
+    }
+#pragma unroll
+    for (int q = 0; q < NMAX; ++q) {
+      if (q >= R) break;
+      const double br = __shfl(xr[q], src, 64);
+      const double bi = __shfl(xi[q], src, 64);
+      xr[q] = xr[q] - lr * br + li * bi;
+      xi[q] = xi[q] - lr * bi - li * br;
+    }
+    if (!me) {
+      ar[k] = 0.0;
+      ai[k] = 0.0;
+    }
+  }
+  if (neg) {
+    res.dre = -res.dre;
+    res.dim = -res.dim;
+  }
+  return res;
+}
+
+// det of the block whose row `rrep` is replaced by the LDS row `newrow`
+// (direct elimination; used when the dominator block had a zero pivot).
+template <int GROUP, int NMAX>
+__device__ __forceinline__ void block_det_direct(const char* lds, uint32_t myrow, int rrep,
+                                                 uint32_t newrow, const uint32_t (&co)[NMAX],
+                                                 int n, int m, double& dre, double& dim) {
+  const uint32_t row = (m == rrep) ? newrow : myrow;
+  double ar[NMAX], ai[NMAX], xr[NMAX], xi[NMAX];
+#pragma unroll
+  for (int c = 0; c < NMAX; ++c) {
+    ar[c] = 0.0;
+    ai[c] = 0.0;
+    if (c < n && m < n) {
+      const double2 v = *reinterpret_cast<const double2*>(lds + row + co[c]);
+      ar[c] = v.x;
+      ai[c] = v.y;
+    }
+  }
+  double ur, ui;
+  int col;
+  const GJResult g = gauss_jordan<GROUP, NMAX>(ar, ai, xr, xi, 0, n, m, ur, ui, col);
+  dre = g.dre;
+  dim = g.dim;
+}
+
+template <int GROUP, int NMAX, bool TREE, int MODE>
+__global__ __launch_bounds__(kWideBlock) void contract_wide_kernel(ContractArgs a) {
+  constexpr bool WITH_A = (MODE & 1) != 0;
+  constexpr bool WITH_PAIRS = (MODE & 2) != 0;
+  constexpr int SPW = kWave / GROUP;   // sinks per wave
+  extern __shared__ double2 smem[];
+  const PlanView& p = a.plan;
+  const int t = blockIdx.y;
+  const int chunk = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = uniform(threadIdx.x / kWave);
+  const int m = lane % GROUP;          // row of the matrix held by this lane
+  const int gsel = lane / GROUP;       // which sink of the wave
+  const int MM = p.M * p.M;
+  const double2* St = a.S + (size_t)t * MM;
+  for (int e = threadIdx.x; e < MM; e += kWideBlock) smem[e] = St[e];
+  __syncthreads();
+  const char* lds = reinterpret_cast<const char*>(smem);
+
+  double acc_re = 0.0, acc_im = 0.0, acc_a = 0.0;
+  uint32_t n_fallback = 0;
+  const int F = p.F;
+  const int sn = p.sn;
+
+  for (int item = chunk + a.n_blk_t * wave; item < a.n_items;
+       item += a.n_blk_t * kWideWaves) {
+    const int d = uniform(item / a.n_sblk);
+    const int sb = uniform(item - d * a.n_sblk);
+    const int k = sb * SPW + gsel;
+    const bool valid = k < p.n_snk;
+    const int term = TREE ? uniform(p.dom_term[d]) : d;
+    const uint32_t* rowoff_d = (TREE ? p.dom_rowoff : p.src_rowoff) + (size_t)d * sn;
+    const double wi = a.w_src[term];
+    const double wk = valid ? a.w_snk[k] : 0.0;
+    const int g_begin = TREE ? uniform(p.dom_grp[d]) : 0;
+    const int g_end = TREE ? uniform(p.dom_grp[d + 1]) : 0;
+    const bool writer = valid && m == 0;
+
+    double Pre = 1.0, Pim = 0.0, Qre = 0.0, Qim = 0.0;
+    double Xre = 1.0, Xim = 0.0;     // product of the non-singular blocks
+    double sabs_reg = 0.0, sabs_fb = 0.0;
+    int nbad = 0, fbad = -1;
+
+    // Test hook: a child's det is ratio * det_f * prod_{g != f} det_g; the
+    // other blocks' dets come from a first pass (the child's own block uses
+    // the elimination its ratio came from).
+    double Dpre_re[kPairFlavors], Dpre_im[kPairFlavors];
+    if (WITH_PAIRS) {
+#pragma unroll
+      for (int f = 0; f < kPairFlavors; ++f) {
+        Dpre_re[f] = 1.0;
+        Dpre_im[f] = 0.0;
+        if (f < F) {
+          const int o = p.off[f];
+          const int n = p.off[f + 1] - o;
+          uint32_t co[NMAX];
+#pragma unroll
+          for (int c = 0; c < NMAX; ++c)
+            co[c] = c < n ? p.snk_coloff[(size_t)(o + c) * p.n_snk_pad + k] : 0u;
+          const uint32_t myrow = m < n ? rowoff_d[o + m] : 0u;
+          block_det_direct<GROUP, NMAX>(lds, myrow, -1, 0u, co, n, m, Dpre_re[f], Dpre_im[f]);
+        }
+      }
+    }
+
+    int g = g_begin;
+    for (int f = 0; f < F; ++f) {
+      const int o = p.off[f];
+      const int n = p.off[f + 1] - o;
+      uint32_t co[NMAX];
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c)
+        co[c] = c < n ? p.snk_coloff[(size_t)(o + c) * p.n_snk_pad + k] : 0u;
+      const uint32_t myrow = m < n ? rowoff_d[o + m] : 0u;
+      double ar[NMAX], ai[NMAX], xr[NMAX], xi[NMAX];
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) {
+        ar[c] = 0.0;
+        ai[c] = 0.0;
+        if (c < n && m < n) {
+          const double2 v = *reinterpret_cast<const double2*>(lds + myrow + co[c]);
+          ar[c] = v.x;
+          ai[c] = v.y;
+        }
+      }
+      int g_f_end = g;
+      if (TREE) {
+        while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
+      }
+      const int R = g_f_end - g;
+      // appended unit columns: E[m][q] = (m == r_q)
+#pragma unroll
+      for (int q = 0; q < NMAX; ++q) {
+        xr[q] = 0.0;
+        xi[q] = 0.0;
+        if (q < R) xr[q] = (m == uniform(p.grp_fr[g + q] & 0xff)) ? 1.0 : 0.0;
+      }
+      double ur, ui;
+      int col;
+      const GJResult res = gauss_jordan<GROUP, NMAX>(ar, ai, xr, xi, R, n, m, ur, ui, col);
+      const double dre = res.dre, dim = res.dim;
+      const bool zero = res.zero;
+      // this lane's pivot column: its sink column offset
+      uint32_t mycol = 0;
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c)
+        if (c == col) mycol = co[c];
+      double accre = 0.0, accim = 0.0;
+      if (TREE && R > 0) {
+        double sre = 0.0, sim = 0.0;
+#pragma unroll
+        for (int q = 0; q < NMAX; ++q) {
+          if (q >= R) break;
+          // x[col] = E'_m / u_m for this group's column r_q
+          const double x_r = xr[q] * ur - xi[q] * ui;
+          const double x_i = xr[q] * ui + xi[q] * ur;
+          const int gg = g + q;
+          const int c_begin = uniform(p.grp_ptr[gg]);
+          const int c_end = uniform(p.grp_ptr[gg + 1]);
+          for (int c = c_begin; c < c_end; ++c) {
+            const uint32_t crow = uniform(p.child_rowoff[c]);
+            const int cterm = uniform(p.child_term[c]);
+            double pr_ = 0.0, pi_ = 0.0;
+            if (m < n) {
+              const double2 s = *reinterpret_cast<const double2*>(lds + crow + mycol);
+              pr_ = s.x * x_r - s.y * x_i;
+              pi_ = s.x * x_i + s.y * x_r;
+            }
+            const double rr = group_sum<GROUP>(pr_);
+            const double ri = group_sum<GROUP>(pi_);
+            const double wc = a.w_src[cterm];
+            sre += wc * rr;
+            sim += wc * ri;
+            if (WITH_A && !zero) sabs_reg += fabs(wc) * sqrt(rr * rr + ri * ri);
+            if (WITH_PAIRS && writer && a.pair_det && !zero) {
+              double cr = rr * dre - ri * dim, ci = rr * dim + ri * dre;
+#pragma unroll
+              for (int h = 0; h < kPairFlavors; ++h) {
+                if (h == f || h >= F) continue;
+                const double tr = cr * Dpre_re[h] - ci * Dpre_im[h];
+                ci = cr * Dpre_im[h] + ci * Dpre_re[h];
+                cr = tr;
+              }
+              a.pair_det[((size_t)t * p.n_src + cterm) * p.n_snk + k] = make_double2(cr, ci);
+            }
+          }
+        }
+        accre = zero ? 0.0 : dre * sre - dim * sim;
+        accim = zero ? 0.0 : dre * sim + dim * sre;
+      }
+      if (zero) {
+        ++nbad;
+        fbad = (TREE && R > 0) ? f : -2;
+      }
+      g = g_f_end;
+      const double qr = Qre * dre - Qim * dim + accre * Pre - accim * Pim;
+      const double qi = Qre * dim + Qim * dre + accre * Pim + accim * Pre;
+      Qre = qr;
+      Qim = qi;
+      const double pr2 = Pre * dre - Pim * dim;
+      Pim = Pre * dim + Pim * dre;
+      Pre = pr2;
+      if (!zero) {
+        const double xr2 = Xre * dre - Xim * dim;
+        Xim = Xre * dim + Xim * dre;
+        Xre = xr2;
+      }
+    }
+
+    if (TREE) {
+      // children of a singular block (the only singular one): direct
+      const bool need = valid && nbad == 1 && fbad >= 0;
+      if (__builtin_amdgcn_ballot_w64(need) != 0) {
+        for (int f = 0; f < F; ++f) {
+          if (__builtin_amdgcn_ballot_w64(need && fbad == f) == 0) continue;
+          const int o = p.off[f];
+          const int n = p.off[f + 1] - o;
+          uint32_t co[NMAX];
+#pragma unroll
+          for (int c = 0; c < NMAX; ++c)
+            co[c] = c < n ? p.snk_coloff[(size_t)(o + c) * p.n_snk_pad + k] : 0u;
+          const uint32_t myrow = m < n ? rowoff_d[o + m] : 0u;
+          double fre = 0.0, fim = 0.0;
+          for (int gg = g_begin; gg < g_end; ++gg) {
+            if (uniform(p.grp_fr[gg] >> 8) != f) continue;
+            const int r = uniform(p.grp_fr[gg] & 0xff);
+            for (int c = uniform(p.grp_ptr[gg]); c < uniform(p.grp_ptr[gg + 1]); ++c) {
+              const uint32_t crow = uniform(p.child_rowoff[c]);
+              const int cterm = uniform(p.child_term[c]);
+              double cre, cim;
+              block_det_direct<GROUP, NMAX>(lds, myrow, r, crow, co, n, m, cre, cim);
+              if (need && fbad == f) {
+                const double wc = a.w_src[cterm];
+                fre += wc * cre;
+                fim += wc * cim;
+                const double dr = cre * Xre - cim * Xim, di = cre * Xim + cim * Xre;
+                if (WITH_A) sabs_fb += fabs(wc) * sqrt(dr * dr + di * di);
+                if (WITH_PAIRS && writer && a.pair_det)
+                  a.pair_det[((size_t)t * p.n_src + cterm) * p.n_snk + k] = make_double2(dr, di);
+                if (m == 0) ++n_fallback;
+              }
+            }
+          }
+          if (need && fbad == f) {
+            Qre += fre * Xre - fim * Xim;
+            Qim += fre * Xim + fim * Xre;
+          }
+        }
+      }
+    }
+
+    if (WITH_PAIRS && a.pair_det && writer) {
+      a.pair_det[((size_t)t * p.n_src + term) * p.n_snk + k] = make_double2(Pre, Pim);
+    }
+    if (writer) {
+      acc_re += wk * (wi * Pre + Qre);
+      acc_im += wk * (wi * Pim + Qim);
+      if (WITH_A) {
+        const double pabs = sqrt(Pre * Pre + Pim * Pim);
+        acc_a += fabs(wk) * ((fabs(wi) + sabs_reg) * pabs + sabs_fb);
+      }
+    }
+  }
+
+  __shared__ double red[kWideWaves][3];
+  const double s0 = wave_sum(acc_re), s1 = wave_sum(acc_im);
+  const double s2 = WITH_A ? wave_sum(acc_a) : 0.0;
+  if (lane == 0) {
+    red[wave][0] = s0;
+    red[wave][1] = s1;
+    red[wave][2] = s2;
+  }
+  if (TREE && a.fallback) {
+    uint32_t nf = n_fallback;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) nf += __shfl_xor(nf, o, kWave);
+    if (lane == 0 && nf) atomicAdd(a.fallback, (unsigned long long)nf);
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWideWaves; ++w) v += red[w][threadIdx.x];
+    a.partial[((size_t)t * a.n_blk_t + chunk) * 3 + threadIdx.x] = v;
+  }
+}
+
+template <int GROUP, int NMAX, bool TREE, int MODE>
+static hipError_t launch_wide_one(const ContractArgs& a, hipStream_t s) {
+  dim3 grid(a.n_blk_t, a.T);
+  const size_t lds = (size_t)a.plan.M * a.plan.M * sizeof(double2);
+  hipError_t e = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&contract_wide_kernel<GROUP, NMAX, TREE, MODE>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((contract_wide_kernel<GROUP, NMAX, TREE, MODE>), grid, dim3(kWideBlock), lds,
+                     s, a);
+  return hipGetLastError();
+}
+
+template <int GROUP, int NMAX>
+static hipError_t launch_wide_n(const ContractArgs& a, bool tree, bool diag, hipStream_t s) {
+  if (tree)
+    return diag ? launch_wide_one<GROUP, NMAX, true, 3>(a, s)
+                : launch_wide_one<GROUP, NMAX, true, 0>(a, s);
+  return diag ? launch_wide_one<GROUP, NMAX, false, 3>(a, s)
+              : launch_wide_one<GROUP, NMAX, false, 0>(a, s);
+}
+
+int wide_sinks_per_wave(int nmax) { return nmax <= 16 ? kWave / 16 : kWave / 32; }
+
+hipError_t launch_contract_wide(const ContractArgs& a, int nmax, bool tree, bool diag,
+                                double2* C, double* A, hipStream_t s) {
+  hipError_t e;
+  if (nmax <= 8)
+    e = launch_wide_n<16, 8>(a, tree, diag, s);
+  else if (nmax <= 12)
+    e = launch_wide_n<16, 12>(a, tree, diag, s);
+  else if (nmax <= 16)
+    e = launch_wide_n<16, 16>(a, tree, diag, s);
+  else if (nmax <= 24)
+    e = launch_wide_n<32, 24>(a, tree, diag, s);
+  else
+    return hipErrorInvalidValue;
+  if (e != hipSuccess) return e;
+  return launch_reduce(a, C, A, s);
+}
+
+}  // namespace kern
+}  // namespace mhc

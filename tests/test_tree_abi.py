@@ -161,9 +161,13 @@ def test_plan_shape_mismatch_is_reported_before_device_work():
     for snk in (mhc.Terms([[0, 1, 2]], (2, 1), 11), mhc.Terms([[0, 1, 2]], (1, 2), 10),
                 mhc.Terms([[0, 1]], (2,), 10)):
         assert L.mhc_plan_create(tree.handle, snk.handle, None, ctypes.byref(h)) == -3
-    # blocks above the kernels' limit are refused as unsupported
-    src = mhc.Terms([list(range(9))], (9,), 20)
-    snk = mhc.Terms([list(range(9))], (9,), 20)
+    # blocks above the kernels' limit are refused as unsupported (checked
+    # before any device work)
+    src = mhc.Terms([list(range(25))], (25,), 30)
+    snk = mhc.Terms([list(range(25))], (25,), 30)
+    assert L.mhc_plan_create(mhc.Tree(src).handle, snk.handle, None, ctypes.byref(h)) == -7
+    src = mhc.Terms([[0, 1]], (2,), 100)
+    snk = mhc.Terms([[0, 1]], (2,), 100)
     assert L.mhc_plan_create(mhc.Tree(src).handle, snk.handle, None, ctypes.byref(h)) == -7
 
 
