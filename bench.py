@@ -1,13 +1,15 @@
 """Benchmark: complex128 det-pairs/s of the update-tree contraction against
 the plain batched LU on the same GPU.
 
-    python bench.py [--steps K] [--warmup W] [--workload mid]
+    python bench.py [--steps K] [--warmup W] [--workload mid|large|batch]
 
 One step = one update-tree contraction of every (slice, source term, sink
 term) pair of the workload (gather, dominator LU, column solves, sibling
 ratios, weighted reduction: one call of mhc_contract).  Inputs (propagator,
 weights, plan) are resident on the GPU before timing starts.  The plain
 batched LU is timed the same way on the same inputs and reported beside it.
+With ``--workload batch`` a step is one run of the 256-job batch (one graph
+launch of mhc_batch_run over every job).
 
 Prints one JSON line.  Runs on one GPU only.
 """
@@ -41,22 +43,29 @@ def f_ratio(n: int) -> int:
     return 8 * n + 12 + 5
 
 
-def tree_flops(T, n_snk, nf, st) -> float:
-    n = nf[0]
-    F = len(nf)
-    per_sink = (st["n_dom"] * (F * f_lu(n) + 11) + st["n_groups"] * f_solve(n)
-                + st["n_children"] * f_ratio(n))
+def tree_flops(T, n_snk, nf, tree) -> float:
+    """Per (slice, sink): every dominator's blocks factorised (and the
+    weighted product), one solve per (dominator, flavour, changed row) group
+    and one ratio per child, each at its own flavour's block size; ``tree``
+    is the exported tree (owner, flavour and row of every term)."""
+    import numpy as np
+    owner, flav, pos = tree["owner"], tree["flav"], tree["pos"]
+    child = owner != np.arange(len(owner))
+    per_sink = tree["n_dom"] * float(sum(f_lu(n) for n in nf) + 11)
+    groups = set(zip(owner[child].tolist(), flav[child].tolist(), pos[child].tolist()))
+    per_sink += sum(f_solve(nf[f]) for _, f, _ in groups)
+    per_sink += sum(f_ratio(nf[f]) for f in flav[child].tolist())
     return float(T) * n_snk * per_sink
 
 
 def plain_flops(T, n_src, n_snk, nf) -> float:
-    n = nf[0]
-    return float(T) * n_src * n_snk * (len(nf) * f_lu(n) + 11)
+    return float(T) * n_src * n_snk * (sum(f_lu(n) for n in nf) + 11)
 
 
 def cpu_baseline(w, target_s: float = 15.0):
-    """The CPU oracle on a bounded sample of the same workload: slice 0,
-    the first source terms x all sink terms, over worker processes."""
+    """The CPU oracle on a bounded sample of the same workload: the first
+    slices (or, below one slice, the first source terms of slice 0) x all
+    sink terms, over worker processes."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import oracle_pool
     n_workers = oracle_pool.workers()
@@ -67,15 +76,125 @@ def cpu_baseline(w, target_s: float = 15.0):
                            n_workers=1)
     dt = time.perf_counter() - t0
     per_pair = dt / (rows * len(w.snk))
-    n_rows = int(min(len(w.src), max(rows, target_s * n_workers / (per_pair * len(w.snk)))))
+    want = target_s * n_workers / per_pair          # pairs in ~target_s
+    slice_pairs = len(w.src) * len(w.snk)
+    if want >= slice_pairs:
+        n_sl = int(min(w.T, want // slice_pairs))
+        n_rows = len(w.src)
+    else:
+        n_sl = 1
+        n_rows = int(max(rows, want // len(w.snk)))
     t0 = time.perf_counter()
-    oracle_pool.correlator(w.S, w.src[:n_rows], w.snk, w.nf, w.w_src[:n_rows], w.w_snk, [0],
-                           n_workers=n_workers)
+    oracle_pool.correlator(w.S, w.src[:n_rows], w.snk, w.nf, w.w_src[:n_rows], w.w_snk,
+                           list(range(n_sl)), n_workers=n_workers)
     dt = time.perf_counter() - t0
-    pairs = n_rows * len(w.snk)
+    pairs = n_sl * n_rows * len(w.snk)
     return {"value": pairs / dt, "unit": "det-pairs/s", "cores": n_workers, "kind": "oracle",
-            "sample": f"slice 0, source terms 0..{n_rows - 1} x all {len(w.snk)} sink terms "
+            "sample": f"slices 0..{n_sl - 1}, source terms 0..{n_rows - 1} x all "
+                      f"{len(w.snk)} sink terms ({pairs} pairs, {dt:.1f} s)"}
+
+
+def cpu_baseline_batch(ws, pairs_per_job: int = 200_000):
+    """The CPU oracle on a fixed 16-job subset of the batch: per job, slice 0
+    and the first source terms (about pairs_per_job pairs) x all sink terms."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import oracle_pool
+    n_workers = oracle_pool.workers()
+    pairs = 0
+    t0 = time.perf_counter()
+    for w in ws[:16]:
+        rows = max(1, min(len(w.src), pairs_per_job // len(w.snk)))
+        oracle_pool.correlator(w.S, w.src[:rows], w.snk, w.nf, w.w_src[:rows], w.w_snk, [0],
+                               n_workers=n_workers)
+        pairs += rows * len(w.snk)
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "det-pairs/s", "cores": n_workers, "kind": "oracle",
+            "sample": f"jobs 0..15 of the batch, slice 0, about {pairs_per_job} pairs each "
                       f"({pairs} pairs, {dt:.1f} s)"}
+
+
+def bench_batch(args):
+    from paper_1411_3691_amd import workloads as W
+    shapes = W.batch_shapes()
+    ws = [W.batch_job(j, shapes[j]) for j in range(len(shapes))]
+    cpu = None if args.no_cpu_baseline else cpu_baseline_batch(ws)
+
+    import numpy as np
+    import torch
+    from paper_1411_3691_amd import mhc
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    plans, S, a, b, C = [], [], [], [], []
+    fl_tree = fl_plain = 0.0
+    t0 = time.perf_counter()
+    for w in ws:
+        tree = mhc.Tree(mhc.Terms(w.src, w.nf, w.M))
+        plans.append(mhc.Plan(tree, mhc.Terms(w.snk, w.nf, w.M)))
+        fl_tree += tree_flops(w.T, len(w.snk), w.nf, tree.export())
+        fl_plain += plain_flops(w.T, len(w.src), len(w.snk), w.nf)
+        S.append(torch.from_numpy(w.S).to(dev))
+        a.append(torch.from_numpy(w.w_src).to(dev))
+        b.append(torch.from_numpy(w.w_snk).to(dev))
+        C.append(torch.empty(w.T, dtype=torch.complex128, device=dev))
+    t_plan = time.perf_counter() - t0
+    pairs = sum(w.n_pairs for w in ws)
+    torch.cuda.synchronize()
+
+    def timed(method):
+        batch = mhc.Batch(plans, [w.T for w in ws], method)
+        for _ in range(args.warmup):
+            batch.run(S, a, b, C)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for e0, e1 in evs:
+            e0.record()
+            batch.run(S, a, b, C)
+            e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = [e0.elapsed_time(e1) for e0, e1 in evs]
+        return wall, float(np.mean(per)), [c.cpu().numpy().copy() for c in C], batch.info()
+
+    wall_tree, ev_tree, C_tree, info = timed("tree")
+    wall_plain, ev_plain, C_plain, _ = timed("plain")
+    rel = max(float(np.max(np.abs(x - y)) / max(1e-300, float(np.max(np.abs(y)))))
+              for x, y in zip(C_tree, C_plain))
+    ach = fl_tree / (ev_tree * 1e-3) / 1e12
+    nfs = sorted({n for w in ws for n in w.nf})
+    out = {
+        "metric": METRIC,
+        "value": pairs / (wall_tree / args.steps),
+        "unit": "det-pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall_tree * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch: {len(ws)} jobs, flavour blocks {nfs[0]}..{nfs[-1]}, "
+                        f"T 8..64, M 24/48/96, 50..5000 tree terms per side",
+            "pairs_per_step": pairs,
+            "method": "update tree (greedy R2 dominating set), one graph launch",
+        },
+        "plain_lu": {"value": pairs / (wall_plain / args.steps),
+                     "ms_per_step": wall_plain * 1e3 / args.steps, "kernel_ms": ev_plain,
+                     "flops_per_step": fl_plain,
+                     "tflops": fl_plain / (ev_plain * 1e-3) / 1e12},
+        "speedup_vs_plain": wall_plain / wall_tree,
+        "tree_vs_plain_max_rel_diff": rel,
+        "tree": {"kernel_ms": ev_tree, "flops_per_step": fl_tree, "plan_s": t_plan, **info},
+        "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -91,6 +210,9 @@ def main():
               "in this library (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batch":
+        bench_batch(args)
+        return
     from paper_1411_3691_amd import workloads as W
     w = W.workload(args.workload)
     # CPU leg first, before the process touches the GPU
@@ -138,7 +260,7 @@ def main():
     ms_plain = wall_plain * 1e3 / args.steps
     ev_tree_ms = float(np.mean(ev_tree))
     ev_plain_ms = float(np.mean(ev_plain))
-    fl_tree = tree_flops(w.T, len(w.snk), w.nf, st)
+    fl_tree = tree_flops(w.T, len(w.snk), w.nf, tree.export())
     fl_plain = plain_flops(w.T, len(w.src), len(w.snk), w.nf)
     ach = fl_tree / (ev_tree_ms * 1e-3) / 1e12
     rel = float(np.max(np.abs(C_tree - C_plain)) / max(1e-300, float(np.max(np.abs(C_plain)))))

@@ -179,6 +179,53 @@ mhc_status mhc_contract_backward(mhc_plan* plan, int32_t T, const void* S,
 mhc_status mhc_plan_status(mhc_plan* plan, int64_t* n_fallback,
                            int64_t* n_singular_grad);
 
+/* Batched jobs.  Many independent contractions (each a plan, its number of
+ * slices and its own buffers) run as one captured graph: one persistent
+ * kernel per kernel variant walks a table of (job, slice, chunk) tiles,
+ * largest predicted cost first, then one kernel writes every job's C (and
+ * A).  The paper notes that partitions of the work can be evaluated
+ * independently (Sec. 5); here independent jobs share one launch.
+ *
+ * Schedule (every field 0 = chosen by the library):
+ *   kernel          MHC_SCHED_AUTO: one matrix per lane where every flavour
+ *                   block of a job has the same size n <= 8, else a group of
+ *                   lanes per matrix; MHC_SCHED_LANE / MHC_SCHED_GROUP force
+ *                   one (LANE is refused for other jobs);
+ *   blocks_per_cu   persistent workgroups per compute unit, in [0, 8];
+ *   items_per_tile  work items per tile, >= 0.
+ * The graph is captured at the first mhc_batch_run and replayed after that
+ * (captured again, after waiting for the device, when a run asks for A and
+ * the previous did not, or the reverse); the method, the slices per job and
+ * the schedule are fixed at creation.
+ * Buffers per job j (device, caller-owned): S[j] complex128 [T[j]][M][M],
+ * w_src[j], w_snk[j], C[j] complex128 [T[j]], A[j] double [T[j]] (A may be
+ * NULL, or any A[j]).  When the buffer pointers differ from the previous
+ * run, mhc_batch_run first waits for the device, then updates the job
+ * table.  Plans must outlive the batch.  Two runs of one batch that
+ * overlap in time (on different streams) share its partial sums and race.
+ * Errors: MHC_E_ARG (NULL handle or buffer, bad schedule, T outside
+ * [1, 65535]), MHC_E_DEVICE (plan or current device differ),
+ * MHC_E_UNSUPPORTED (LANE forced on a job it cannot run), MHC_E_OOM. */
+enum { MHC_SCHED_AUTO = 0, MHC_SCHED_LANE = 1, MHC_SCHED_GROUP = 2 };
+typedef struct {
+  int32_t kernel;
+  int32_t blocks_per_cu;
+  int32_t items_per_tile;
+} mhc_schedule;
+typedef struct mhc_batch mhc_batch;
+
+mhc_status mhc_batch_create(mhc_plan* const* plans, const int32_t* T, int32_t n_jobs,
+                            int32_t method, const mhc_schedule* sched, mhc_batch** out);
+mhc_status mhc_batch_run(mhc_batch* batch, const void* const* S,
+                         const double* const* w_src, const double* const* w_snk,
+                         void* const* C, double* const* A, void* stream);
+/* Tiles, kernels in the graph (persistent kernels + 1), and det-pairs per
+ * run (sum over jobs of T * n_src * n_snk); tiles and kernels are 0 before
+ * the first run. */
+mhc_status mhc_batch_info(const mhc_batch* batch, int32_t* n_tiles, int32_t* n_kernels,
+                          int64_t* n_pairs);
+void mhc_batch_destroy(mhc_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

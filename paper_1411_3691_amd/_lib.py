@@ -24,6 +24,17 @@ GREEDY_R1 = 1
 GREEDY_R2 = 2
 PLAIN_LU = 0
 UPDATE_TREE = 1
+SCHED_AUTO = 0
+SCHED_LANE = 1
+SCHED_GROUP = 2
+
+
+class Schedule(ctypes.Structure):
+    """mhc_schedule: kernel family, persistent workgroups per CU, items per
+    tile (0 = the library's choice)."""
+    _fields_ = [("kernel", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("items_per_tile", ctypes.c_int32)]
+
 
 # Every function the C header declares, with its ctypes signature.
 _P = ctypes.c_void_p
@@ -47,6 +58,12 @@ SIGNATURES = {
     "mhc_contract": (_I32, [_P, _I32, _I32, _P, _PD, _PD, _P, _PD, _P, _P]),
     "mhc_contract_backward": (_I32, [_P, _I32, _P, _PD, _PD, _P, _P, _PD, _PD, _P]),
     "mhc_plan_status": (_I32, [_P, _PI64, _PI64]),
+    "mhc_batch_create": (_I32, [ctypes.POINTER(_P), _PI32, _I32, _I32, ctypes.POINTER(Schedule),
+                                ctypes.POINTER(_P)]),
+    "mhc_batch_run": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                             ctypes.POINTER(_P), ctypes.POINTER(_P), _P]),
+    "mhc_batch_info": (_I32, [_P, _PI32, _PI32, _PI64]),
+    "mhc_batch_destroy": (None, [_P]),
 }
 
 

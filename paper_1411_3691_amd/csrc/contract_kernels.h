@@ -35,6 +35,16 @@ struct ContractArgs {
   double2* pair_det;              // [T][n_src][n_snk] or null
   unsigned long long* fallback;   // fallback counter or null
   int T, n_items, n_blk_t, n_sblk;
+  double2* C;                     // outputs, read by the batch reduction only
+  double* A;
+};
+
+// A batch of jobs for one persistent kernel: tile i = (job, t, chunk, 0)
+// in processing order.
+struct BatchArgs {
+  const ContractArgs* jobs;
+  const int4* tiles;
+  int n_tiles;
 };
 
 // Flavour blocks supported by the pair-determinant test hook.
@@ -56,6 +66,17 @@ int wide_sinks_per_wave(int nmax);
 
 // Final fixed-order reduction of the workgroup partials into C (and A).
 hipError_t launch_reduce(const ContractArgs& a, double2* C, double* A, hipStream_t s);
+
+// Persistent kernels over a tile table (grid workgroups, lds bytes of
+// dynamic LDS = the largest slice of S among the jobs); with_a: the
+// partials also carry the scale A.
+hipError_t launch_batch_lane(const BatchArgs& b, int n, bool tree, bool with_a, int grid,
+                             size_t lds, hipStream_t s);
+hipError_t launch_batch_wide(const BatchArgs& b, int nmax, bool tree, bool with_a, int grid,
+                             size_t lds, hipStream_t s);
+int wide_bucket(int nmax);
+// C_j[t] for each entry (job, t) of jt (n entries).
+hipError_t launch_batch_reduce(const ContractArgs* jobs, const int2* jt, int n, hipStream_t s);
 
 }  // namespace kern
 }  // namespace mhc

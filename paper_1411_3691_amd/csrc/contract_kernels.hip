@@ -61,14 +61,16 @@ __device__ __forceinline__ void child_det_direct(const char* lds,
 }
 
 // MODE bit 0: accumulate A(t) = sum |w w d|; bit 1: write every pair det.
+// One tile: slice t, the chunk-th strided share of the slice's work items.
+// The workgroup stages S_t in LDS (smem), walks its items and writes one
+// partial (re, im, A) for (t, chunk).
 template <int N, bool TREE, int MODE>
-__global__ __launch_bounds__(kBlock, 2) void contract_kernel(ContractArgs a) {
+__device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chunk,
+                                          double2* smem) {
   constexpr bool WITH_A = (MODE & 1) != 0;
   constexpr bool WITH_PAIRS = (MODE & 2) != 0;
-  extern __shared__ double2 smem[];
   const PlanView& p = a.plan;
-  const int t = blockIdx.y;
-  const int chunk = blockIdx.x;
+  __syncthreads();  // the previous tile of this workgroup is done with LDS
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uniform(threadIdx.x / kWave);
   const int MM = p.M * p.M;
@@ -314,6 +316,23 @@ __global__ __launch_bounds__(kBlock, 2) void contract_kernel(ContractArgs a) {
   }
 }
 
+template <int N, bool TREE, int MODE>
+__global__ __launch_bounds__(kBlock, 2) void contract_kernel(ContractArgs a) {
+  extern __shared__ double2 smem[];
+  lane_tile<N, TREE, MODE>(a, blockIdx.y, blockIdx.x, smem);
+}
+
+// Persistent form: workgroup w takes tiles w, w + gridDim.x, ... of a tile
+// table spanning many jobs.
+template <int N, bool TREE, int MODE>
+__global__ __launch_bounds__(kBlock, 2) void batch_lane_kernel(BatchArgs b) {
+  extern __shared__ double2 smem[];
+  for (int i = blockIdx.x; i < b.n_tiles; i += gridDim.x) {
+    const int4 tl = b.tiles[i];
+    lane_tile<N, TREE, MODE>(b.jobs[tl.x], tl.y, tl.z, smem);
+  }
+}
+
 // C[t] = sum over workgroups of the partials, in a fixed order.
 __global__ __launch_bounds__(kBlock) void reduce_partials(const double* partial, int n_blk_t,
                                                           double2* C, double* A) {
@@ -371,6 +390,71 @@ hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag,
   }
   if (e != hipSuccess) return e;
   return launch_reduce(a, C, A, s);
+}
+
+template <int N, bool TREE, int MODE>
+static hipError_t launch_batch_lane_m(const BatchArgs& b, int grid, size_t lds, hipStream_t s) {
+  hipError_t e =
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_lane_kernel<N, TREE, MODE>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((batch_lane_kernel<N, TREE, MODE>), dim3(grid), dim3(kBlock), lds, s, b);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_batch_lane_n(const BatchArgs& b, bool tree, bool with_a, int grid,
+                                      size_t lds, hipStream_t s) {
+  if (tree)
+    return with_a ? launch_batch_lane_m<N, true, 1>(b, grid, lds, s)
+                  : launch_batch_lane_m<N, true, 0>(b, grid, lds, s);
+  return with_a ? launch_batch_lane_m<N, false, 1>(b, grid, lds, s)
+                : launch_batch_lane_m<N, false, 0>(b, grid, lds, s);
+}
+
+hipError_t launch_batch_lane(const BatchArgs& b, int n, bool tree, bool with_a, int grid,
+                             size_t lds, hipStream_t s) {
+  switch (n) {
+#define MHC_CASE(NN)                                                             \
+  case NN:                                                                       \
+    return launch_batch_lane_n<NN>(b, tree, with_a, grid, lds, s);
+    MHC_CASE(1) MHC_CASE(2) MHC_CASE(3) MHC_CASE(4) MHC_CASE(5) MHC_CASE(6) MHC_CASE(7)
+    MHC_CASE(8)
+#undef MHC_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// C_j[t] for every (job, slice) of a batch: one workgroup per entry of pairs
+// (job, t), summing that job's partials in a fixed order.
+__global__ __launch_bounds__(kBlock) void batch_reduce(const ContractArgs* jobs, const int2* jt) {
+  const int2 e = jt[blockIdx.x];
+  const ContractArgs& a = jobs[e.x];
+  const int t = e.y;
+  __shared__ double red[3][kBlock];
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < a.n_blk_t; b += kBlock)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c] += a.partial[((size_t)t * a.n_blk_t + b) * 3 + c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.C[t] = make_double2(red[0][0], red[1][0]);
+    if (a.A) a.A[t] = red[2][0];
+  }
+}
+
+hipError_t launch_batch_reduce(const ContractArgs* jobs, const int2* jt, int n, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reduce, dim3(n), dim3(kBlock), 0, s, jobs, jt);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const ContractArgs& a, double2* C, double* A, hipStream_t s) {

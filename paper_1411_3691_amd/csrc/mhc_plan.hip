@@ -347,3 +347,313 @@ mhc_status mhc_plan_status(mhc_plan* pl, int64_t* n_fallback,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- batches
+//
+// Many independent jobs (plan, slices, method) run as one graph: one
+// persistent kernel per kernel variant walks a tile table (job, slice,
+// chunk) sorted by predicted cost (largest first, dealt round-robin to the
+// workgroups), then one kernel reduces every job's partials.  The graph is
+// captured at the first run and replayed afterwards.
+
+struct mhc_batch {
+  int device = 0;
+  int32_t method = MHC_UPDATE_TREE;
+  mhc_schedule sched{};
+  std::vector<mhc_plan*> plans;
+  std::vector<int32_t> T;
+  bool built = false;
+  bool with_a = false;               // the captured kernels carry A
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  mhc::kern::ContractArgs* jobs_host = nullptr;  // pinned
+  void* dev = nullptr;                           // jobs, tiles, (job, t), partials
+  mhc::kern::ContractArgs* jobs_dev = nullptr;
+  int n_tiles = 0, n_kernels = 0, n_jt = 0;
+  int64_t n_pairs = 0;
+  std::vector<const void*> last_ptrs;
+};
+
+namespace {
+
+struct Bucket {
+  bool narrow;
+  int n;          // block size (narrow) or bucket bound (group of lanes)
+  size_t lds;
+  std::vector<int4> tiles;
+  std::vector<double> cost;
+};
+
+void batch_release(mhc_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->dev) hipFree(b->dev);
+  if (b->jobs_host) hipHostFree(b->jobs_host);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->cap = nullptr;
+  b->dev = nullptr;
+  b->jobs_host = nullptr;
+  b->built = false;
+}
+
+bool use_lane_kernel(const mhc_plan* pl, int32_t kernel) {
+  if (kernel == MHC_SCHED_LANE) return true;
+  if (kernel == MHC_SCHED_GROUP) return false;
+  return pl->uniform_n && pl->n <= 8;
+}
+
+mhc_status batch_build(mhc_batch* b) {
+  const int nj = (int)b->plans.size();
+  int n_cu = 0;
+  hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/attribute");
+  const bool tree = b->method == MHC_UPDATE_TREE;
+  std::vector<mhc::kern::ContractArgs> jobs(nj);
+  std::vector<size_t> part_off(nj);
+  size_t part_total = 0;
+  std::vector<Bucket> buckets;
+  std::vector<int2> jt;
+  b->n_pairs = 0;
+  for (int j = 0; j < nj; ++j) {
+    mhc_plan* pl = b->plans[j];
+    const bool narrow = use_lane_kernel(pl, b->sched.kernel);
+    const int spi = narrow ? kSinkBlock : mhc::kern::wide_sinks_per_wave(pl->n);
+    const int rowsets = tree ? pl->n_dom : pl->n_src;
+    const int n_sblk = (pl->n_snk + spi - 1) / spi;
+    const long long n_items = (long long)rowsets * n_sblk;
+    if (n_items > 0x7fffffffLL) return fail(MHC_E_UNSUPPORTED, "mhc_batch_run: job too large");
+    const int ipt = b->sched.items_per_tile > 0 ? b->sched.items_per_tile : (narrow ? 64 : 32);
+    const int n_blk_t = (int)std::max<long long>(1, (n_items + ipt - 1) / ipt);
+    mhc::kern::ContractArgs& a = jobs[j];
+    a = mhc::kern::ContractArgs{};
+    a.plan = pl->view;
+    a.fallback = pl->fallback;
+    a.T = b->T[j];
+    a.n_items = (int)n_items;
+    a.n_blk_t = n_blk_t;
+    a.n_sblk = n_sblk;
+    part_off[j] = part_total;
+    part_total += (size_t)a.T * n_blk_t * 3;
+    b->n_pairs += (int64_t)a.T * pl->n_src * pl->n_snk;
+    // predicted cost of one item: the eliminations, the solves, the dots
+    double item = 0.0;
+    for (int f = 0; f < pl->F; ++f) {
+      const double nf = pl->off[f + 1] - pl->off[f];
+      item += nf * nf * nf;
+    }
+    if (tree && pl->n_dom > 0)
+      item += (double)pl->n_groups / pl->n_dom * pl->n * pl->n +
+              (double)pl->n_children / pl->n_dom * pl->n;
+    item *= spi;
+    const int key_n = narrow ? pl->n : mhc::kern::wide_bucket(pl->n);
+    Bucket* bk = nullptr;
+    for (auto& x : buckets)
+      if (x.narrow == narrow && x.n == key_n) bk = &x;
+    if (!bk) {
+      buckets.push_back(Bucket{narrow, key_n, 0, {}, {}});
+      bk = &buckets.back();
+    }
+    bk->lds = std::max(bk->lds, (size_t)pl->M * pl->M * 16);
+    for (int t = 0; t < a.T; ++t) {
+      jt.push_back(make_int2(j, t));
+      for (int c = 0; c < n_blk_t; ++c) {
+        const long long its = (n_items - c + n_blk_t - 1) / n_blk_t;  // items of chunk c
+        bk->tiles.push_back(make_int4(j, t, c, 0));
+        bk->cost.push_back(item * (double)its);
+      }
+    }
+  }
+  // largest tiles first within each persistent kernel
+  std::vector<int4> tiles;
+  std::vector<std::pair<size_t, size_t>> ranges;
+  for (auto& bk : buckets) {
+    std::vector<size_t> order(bk.tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return bk.cost[x] > bk.cost[y]; });
+    ranges.push_back({tiles.size(), order.size()});
+    for (size_t i : order) tiles.push_back(bk.tiles[i]);
+  }
+  // device image: jobs | tiles | (job, t) | partials
+  const size_t o_jobs = 0;
+  const size_t o_tiles = (o_jobs + nj * sizeof(mhc::kern::ContractArgs) + 255) & ~size_t(255);
+  const size_t o_jt = (o_tiles + tiles.size() * sizeof(int4) + 255) & ~size_t(255);
+  const size_t o_part = (o_jt + jt.size() * sizeof(int2) + 255) & ~size_t(255);
+  const size_t bytes = o_part + part_total * sizeof(double);
+  e = hipMalloc(&b->dev, bytes);
+  if (e != hipSuccess) return fail(MHC_E_OOM, "mhc_batch_run: device scratch");
+  e = hipHostMalloc(reinterpret_cast<void**>(&b->jobs_host), nj * sizeof(mhc::kern::ContractArgs),
+                    hipHostMallocDefault);
+  if (e != hipSuccess) return fail(MHC_E_OOM, "mhc_batch_run: pinned job table");
+  char* base = static_cast<char*>(b->dev);
+  b->jobs_dev = reinterpret_cast<mhc::kern::ContractArgs*>(base + o_jobs);
+  int4* tiles_dev = reinterpret_cast<int4*>(base + o_tiles);
+  int2* jt_dev = reinterpret_cast<int2*>(base + o_jt);
+  double* part_dev = reinterpret_cast<double*>(base + o_part);
+  for (int j = 0; j < nj; ++j) {
+    jobs[j].partial = part_dev + part_off[j];
+    b->jobs_host[j] = jobs[j];
+  }
+  e = hipMemcpy(tiles_dev, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(jt_dev, jt.data(), jt.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/upload");
+  // capture the persistent kernels and the reduction
+  e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/stream");
+  e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/capture");
+  hipError_t le = hipSuccess;
+  for (size_t i = 0; i < buckets.size() && le == hipSuccess; ++i) {
+    const Bucket& bk = buckets[i];
+    mhc::kern::BatchArgs ba{b->jobs_dev, tiles_dev + ranges[i].first, (int)ranges[i].second};
+    int per_cu = b->sched.blocks_per_cu;
+    if (per_cu <= 0) per_cu = bk.lds > 72 * 1024 ? 1 : 2;
+    const int grid = std::max(1, std::min((int)ranges[i].second, n_cu * per_cu));
+    le = bk.narrow
+             ? mhc::kern::launch_batch_lane(ba, bk.n, tree, b->with_a, grid, bk.lds, b->cap)
+             : mhc::kern::launch_batch_wide(ba, bk.n, tree, b->with_a, grid, bk.lds, b->cap);
+  }
+  if (le == hipSuccess) le = mhc::kern::launch_batch_reduce(b->jobs_dev, jt_dev, (int)jt.size(), b->cap);
+  e = hipStreamEndCapture(b->cap, &b->graph);
+  if (le != hipSuccess) return hip_fail(le, "mhc_batch_run/launch");
+  if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/capture end");
+  e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/instantiate");
+  b->n_tiles = (int)tiles.size();
+  b->n_kernels = (int)buckets.size() + 1;
+  b->n_jt = (int)jt.size();
+  b->last_ptrs.clear();
+  b->built = true;
+  return MHC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mhc_status mhc_batch_create(mhc_plan* const* plans, const int32_t* T, int32_t n_jobs,
+                            int32_t method, const mhc_schedule* sched, mhc_batch** out) {
+  if (!out) return fail(MHC_E_ARG, "mhc_batch_create: out is NULL");
+  *out = nullptr;
+  if (!plans || !T || n_jobs < 1) return fail(MHC_E_ARG, "mhc_batch_create: no jobs");
+  if (method != MHC_PLAIN_LU && method != MHC_UPDATE_TREE)
+    return fail(MHC_E_ARG, "mhc_batch_create: unknown method");
+  mhc_schedule sc{};
+  if (sched) sc = *sched;
+  if (sc.kernel < MHC_SCHED_AUTO || sc.kernel > MHC_SCHED_GROUP || sc.blocks_per_cu < 0 ||
+      sc.blocks_per_cu > 8 || sc.items_per_tile < 0)
+    return fail(MHC_E_ARG, "mhc_batch_create: invalid schedule");
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "mhc_batch_create/hipGetDevice");
+  for (int j = 0; j < n_jobs; ++j) {
+    if (!plans[j]) return fail(MHC_E_ARG, "mhc_batch_create: NULL plan");
+    if (plans[j]->device != cur)
+      return fail(MHC_E_DEVICE, "mhc_batch_create: a plan lives on another device");
+    if (T[j] < 1 || T[j] > 65535) return fail(MHC_E_ARG, "mhc_batch_create: T outside [1, 65535]");
+    if (sc.kernel == MHC_SCHED_LANE && !(plans[j]->uniform_n && plans[j]->n <= 8))
+      return fail(MHC_E_UNSUPPORTED,
+                  "mhc_batch_create: the one-matrix-per-lane schedule needs every flavour "
+                  "block of size n <= 8");
+  }
+  mhc_batch* b = new (std::nothrow) mhc_batch();
+  if (!b) return fail(MHC_E_OOM, "mhc_batch_create: out of host memory");
+  b->device = cur;
+  b->method = method;
+  b->sched = sc;
+  b->plans.assign(plans, plans + n_jobs);
+  b->T.assign(T, T + n_jobs);
+  *out = b;
+  return MHC_OK;
+}
+
+mhc_status mhc_batch_run(mhc_batch* b, const void* const* S, const double* const* w_src,
+                         const double* const* w_snk, void* const* C, double* const* A,
+                         void* stream) {
+  if (!b) return fail(MHC_E_ARG, "mhc_batch_run: NULL batch");
+  if (!S || !w_src || !w_snk || !C) return fail(MHC_E_ARG, "mhc_batch_run: NULL pointer array");
+  const int nj = (int)b->plans.size();
+  for (int j = 0; j < nj; ++j)
+    if (!S[j] || !w_src[j] || !w_snk[j] || !C[j])
+      return fail(MHC_E_ARG, "mhc_batch_run: NULL buffer for job " + std::to_string(j));
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/hipGetDevice");
+  if (cur != b->device) return fail(MHC_E_DEVICE, "mhc_batch_run: wrong current device");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool with_a = A != nullptr;
+  if (b->built && b->with_a != with_a) {
+    // the other kernel variants are needed: capture again
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/sync");
+    batch_release(b);
+  }
+  if (!b->built) {
+    b->with_a = with_a;
+    mhc_status st = batch_build(b);
+    if (st != MHC_OK) {
+      batch_release(b);
+      return st;
+    }
+  }
+  std::vector<const void*> ptrs;
+  ptrs.reserve(5 * nj);
+  for (int j = 0; j < nj; ++j) {
+    ptrs.push_back(S[j]);
+    ptrs.push_back(w_src[j]);
+    ptrs.push_back(w_snk[j]);
+    ptrs.push_back(C[j]);
+    ptrs.push_back(A ? A[j] : nullptr);
+  }
+  if (ptrs != b->last_ptrs) {
+    // the job table is read by the graph: let earlier runs finish first,
+    // whichever stream they were launched on
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/sync");
+    for (int j = 0; j < nj; ++j) {
+      b->jobs_host[j].S = static_cast<const double2*>(S[j]);
+      b->jobs_host[j].w_src = w_src[j];
+      b->jobs_host[j].w_snk = w_snk[j];
+      b->jobs_host[j].C = static_cast<double2*>(C[j]);
+      b->jobs_host[j].A = A ? A[j] : nullptr;
+    }
+    e = hipMemcpy(b->jobs_dev, b->jobs_host, nj * sizeof(mhc::kern::ContractArgs),
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/job table");
+    b->last_ptrs = ptrs;
+  }
+  e = hipGraphLaunch(b->exec, s);
+  if (e != hipSuccess) return hip_fail(e, "mhc_batch_run/graph launch");
+  return MHC_OK;
+}
+
+mhc_status mhc_batch_info(const mhc_batch* b, int32_t* n_tiles, int32_t* n_kernels,
+                          int64_t* n_pairs) {
+  if (!b) return fail(MHC_E_ARG, "mhc_batch_info: NULL batch");
+  if (n_tiles) *n_tiles = b->n_tiles;
+  if (n_kernels) *n_kernels = b->n_kernels;
+  if (n_pairs) {
+    int64_t np = 0;
+    for (size_t j = 0; j < b->plans.size(); ++j)
+      np += (int64_t)b->T[j] * b->plans[j]->n_src * b->plans[j]->n_snk;
+    *n_pairs = np;
+  }
+  return MHC_OK;
+}
+
+void mhc_batch_destroy(mhc_batch* b) {
+  if (!b) return;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(b->device);
+  hipDeviceSynchronize();
+  batch_release(b);
+  hipSetDevice(cur);
+  delete b;
+}
+
+}  // extern "C"

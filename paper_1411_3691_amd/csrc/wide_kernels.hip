@@ -6,15 +6,17 @@
 //
 // Per flavour block of a (row set, sink) pair the group runs Gauss-Jordan
 // elimination with partial pivoting (pivot = largest |Re| + |Im| among the
-// rows not yet used, lowest row on ties) on [G | E], where E holds the unit
-// columns e_r of the rows r that the row set's children change.  Eliminating
-// every other row at every step (not only the rows below) costs nothing
-// extra here -- a lane whose row is done would idle otherwise -- and leaves
-// each row m with one non-zero, its pivot u_m in column c_m, so that
-// x = G^-1 e_r has x[c_m] = E'_m / u_m: no triangular solve is needed.
-// det G = sign(pivot order) * prod_k u_k, the same pivots as GEPP.  A child
-// whose row r is replaced by s has det = det G * (s . x) (matrix determinant
-// lemma, Sec. 2): each lane multiplies s[c_m] by x[c_m] and the group sums.
+// rows not yet used, lowest row on ties).  Eliminating every other row at
+// every step (not only the rows below) costs nothing extra here -- a lane
+// whose row is done would idle otherwise -- and leaves each row m with one
+// non-zero, its pivot u_m in column c_m.  det G = sign(pivot order) *
+// prod_k u_k, the same pivots as GEPP.  Each row keeps its multipliers in
+// the columns the elimination zeroed; replaying those row operations on a
+// unit column e_r gives E', and x = G^-1 e_r has x[c_m] = E'_m / u_m: no
+// triangular solve is needed, and no appended columns are carried through
+// the elimination.  A child whose row r is replaced by s has det = det G *
+// (s . x) (matrix determinant lemma, Sec. 2): each lane multiplies s[c_m]
+// by x[c_m] and the group sums.
 //
 // Work decomposition: a wave holds 64 / GROUP sinks of one row set (the
 // tree structure stays wave-uniform); a workgroup stages S_t in LDS and its
@@ -24,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "contract_kernels.h"
 #include "lu_device.h"
@@ -48,22 +51,41 @@ __device__ __forceinline__ double group_max(double v) {
   return v;
 }
 
+// fn(integral_constant<int, i>) for i = B .. E-1: the loop is unrolled in
+// the source, so every array index below is a constant expression and the
+// per-lane rows stay in registers at any NMAX.
+template <int B, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(fn);
+  }
+}
+
 // Result of eliminating one flavour block.
 struct GJResult {
   double dre, dim;   // det G (same value in every lane of the group)
   bool zero;         // some pivot was exactly zero
 };
 
+// Pivot lanes of the elimination steps, 5 bits each.
+template <int NMAX>
+struct PivotLanes {
+  uint32_t w[(NMAX + 5) / 6];
+  __device__ __forceinline__ int get(int k) const { return (w[k / 6] >> (5 * (k % 6))) & 31; }
+};
+
 // Gauss-Jordan on the group's matrix.  (ar, ai)[c]: this lane's row
-// (columns c < n); (xr, xi)[q]: this lane's entries of the R appended unit
-// columns.  On return, lane m < n holds the reciprocal of its pivot in
-// (ur, ui) and the column it pivoted in (col); its appended entries E'_m
-// then give x[col] = E'_m / u_m for each appended column.
+// (columns c < n).  Step k eliminates column k from every row but the
+// pivot row; a row's multiplier l_{m,k} is kept in its column k (which
+// the elimination has just zeroed), so the row operations can be replayed
+// on any right-hand side afterwards (replay_unit).  On return, lane m < n
+// holds the reciprocal of its pivot in (ur, ui) and the column it pivoted
+// in (col); piv holds the pivot lane of every step.
 template <int GROUP, int NMAX>
-__device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai)[NMAX],
-                                                 double (&xr)[NMAX], double (&xi)[NMAX], int R,
-                                                 int n, int m, double& ur, double& ui,
-                                                 int& col) {
+__device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai)[NMAX], int n,
+                                                 int m, double& ur, double& ui, int& col,
+                                                 PivotLanes<NMAX>& piv) {
   static_assert(GROUP <= 32, "lane rank is packed into 5 bits");
   GJResult res{1.0, 0.0, false};
   bool done = m >= n;
@@ -72,9 +94,10 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
   ur = 0.0;
   ui = 0.0;
   col = -1;
-#pragma unroll
-  for (int k = 0; k < NMAX; ++k) {
-    if (k >= n) break;
+  static_for<0, (NMAX + 5) / 6>([&](auto ic) { piv.w[decltype(ic)::value] = 0u; });
+  static_for<0, NMAX>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if (k >= n) return;
     // pivot: largest |Re|+|Im| of column k among rows not used yet
     const double mag = fabs(ar[k]) + fabs(ai[k]);
     const uint32_t lo = (__double2loint(mag) & ~31u) | (uint32_t)(31 - m);
@@ -83,6 +106,7 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
     // (some row of the group is always unused at step k < n, so the max
     // carries a rank 0 <= p < GROUP; the mask only keeps the lane in range)
     const int p = (31 - (int)(__double2loint(key) & 31u)) & (GROUP - 1);
+    piv.w[k / 6] |= (uint32_t)p << (5 * (k % 6));
     // sign: rows below p that are still unused each contribute one
     // transposition to the pivot permutation
     const uint64_t open = __builtin_amdgcn_ballot_w64(!done);
@@ -113,32 +137,49 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
       lr = 0.0;
       li = 0.0;
     }
-#pragma unroll
-    for (int c = k + 1; c < NMAX; ++c) {
-      if (c >= n) break;
+    static_for<k + 1, NMAX>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if (c >= n) return;
       const double br = __shfl(ar[c], src, 64);
       const double bi = __shfl(ai[c], src, 64);
       ar[c] = ar[c] - lr * br + li * bi;
       ai[c] = ai[c] - lr * bi - li * br;
-    }
-#pragma unroll
-    for (int q = 0; q < NMAX; ++q) {
-      if (q >= R) break;
-      const double br = __shfl(xr[q], src, 64);
-      const double bi = __shfl(xi[q], src, 64);
-      xr[q] = xr[q] - lr * br + li * bi;
-      xi[q] = xi[q] - lr * bi - li * br;
-    }
+    });
     if (!me) {
-      ar[k] = 0.0;
-      ai[k] = 0.0;
+      ar[k] = lr;
+      ai[k] = li;
     }
-  }
+  });
   if (neg) {
     res.dre = -res.dre;
     res.dim = -res.dim;
   }
   return res;
+}
+
+// x = G^-1 e_r from an elimination: replays its row operations on the unit
+// column e_r (lane m holds entry m); then x[col_m] = E'_m / u_m, returned
+// in (xr, xi) by lane m.  The pivot lane of a step keeps its own column k
+// entry (its pivot), which the step does not use.
+template <int GROUP, int NMAX>
+__device__ __forceinline__ void replay_unit(const double (&ar)[NMAX], const double (&ai)[NMAX],
+                                            const PivotLanes<NMAX>& piv, int r, int n, int m,
+                                            double ur, double ui, double& xr, double& xi) {
+  const int gbase = (__lane_id() / GROUP) * GROUP;
+  double er = (m == r) ? 1.0 : 0.0, ei = 0.0;
+  static_for<0, NMAX>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if (k >= n) return;
+    const int p = piv.get(k);
+    const double br = __shfl(er, gbase + p, 64);
+    const double bi = __shfl(ei, gbase + p, 64);
+    if (m != p && m < n) {
+      er = er - ar[k] * br + ai[k] * bi;
+      ei = ei - ar[k] * bi - ai[k] * br;
+    }
+  });
+  xr = er * ur - ei * ui;
+  xi = er * ui + ei * ur;
 }
 
 // det of the block whose row `rrep` is replaced by the LDS row `newrow`
@@ -148,7 +189,7 @@ __device__ __forceinline__ void block_det_direct(const char* lds, uint32_t myrow
                                                  uint32_t newrow, const uint32_t (&co)[NMAX],
                                                  int n, int m, double& dre, double& dim) {
   const uint32_t row = (m == rrep) ? newrow : myrow;
-  double ar[NMAX], ai[NMAX], xr[NMAX], xi[NMAX];
+  double ar[NMAX], ai[NMAX];
 #pragma unroll
   for (int c = 0; c < NMAX; ++c) {
     ar[c] = 0.0;
@@ -161,20 +202,21 @@ __device__ __forceinline__ void block_det_direct(const char* lds, uint32_t myrow
   }
   double ur, ui;
   int col;
-  const GJResult g = gauss_jordan<GROUP, NMAX>(ar, ai, xr, xi, 0, n, m, ur, ui, col);
+  PivotLanes<NMAX> piv;
+  const GJResult g = gauss_jordan<GROUP, NMAX>(ar, ai, n, m, ur, ui, col, piv);
   dre = g.dre;
   dim = g.dim;
 }
 
+// One tile (slice t, chunk) of a job, as lane_tile for one matrix per lane.
 template <int GROUP, int NMAX, bool TREE, int MODE>
-__global__ __launch_bounds__(kWideBlock) void contract_wide_kernel(ContractArgs a) {
+__device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chunk,
+                                          double2* smem) {
   constexpr bool WITH_A = (MODE & 1) != 0;
   constexpr bool WITH_PAIRS = (MODE & 2) != 0;
   constexpr int SPW = kWave / GROUP;   // sinks per wave
-  extern __shared__ double2 smem[];
   const PlanView& p = a.plan;
-  const int t = blockIdx.y;
-  const int chunk = blockIdx.x;
+  __syncthreads();  // the previous tile of this workgroup is done with LDS
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uniform(threadIdx.x / kWave);
   const int m = lane % GROUP;          // row of the matrix held by this lane
@@ -240,7 +282,7 @@ __global__ __launch_bounds__(kWideBlock) void contract_wide_kernel(ContractArgs 
       for (int c = 0; c < NMAX; ++c)
         co[c] = c < n ? p.snk_coloff[(size_t)(o + c) * p.n_snk_pad + k] : 0u;
       const uint32_t myrow = m < n ? rowoff_d[o + m] : 0u;
-      double ar[NMAX], ai[NMAX], xr[NMAX], xi[NMAX];
+      double ar[NMAX], ai[NMAX];
 #pragma unroll
       for (int c = 0; c < NMAX; ++c) {
         ar[c] = 0.0;
@@ -256,16 +298,10 @@ __global__ __launch_bounds__(kWideBlock) void contract_wide_kernel(ContractArgs 
         while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
       }
       const int R = g_f_end - g;
-      // appended unit columns: E[m][q] = (m == r_q)
-#pragma unroll
-      for (int q = 0; q < NMAX; ++q) {
-        xr[q] = 0.0;
-        xi[q] = 0.0;
-        if (q < R) xr[q] = (m == uniform(p.grp_fr[g + q] & 0xff)) ? 1.0 : 0.0;
-      }
       double ur, ui;
       int col;
-      const GJResult res = gauss_jordan<GROUP, NMAX>(ar, ai, xr, xi, R, n, m, ur, ui, col);
+      PivotLanes<NMAX> piv;
+      const GJResult res = gauss_jordan<GROUP, NMAX>(ar, ai, n, m, ur, ui, col, piv);
       const double dre = res.dre, dim = res.dim;
       const bool zero = res.zero;
       // this lane's pivot column: its sink column offset
@@ -276,12 +312,11 @@ __global__ __launch_bounds__(kWideBlock) void contract_wide_kernel(ContractArgs 
       double accre = 0.0, accim = 0.0;
       if (TREE && R > 0) {
         double sre = 0.0, sim = 0.0;
-#pragma unroll
-        for (int q = 0; q < NMAX; ++q) {
-          if (q >= R) break;
-          // x[col] = E'_m / u_m for this group's column r_q
-          const double x_r = xr[q] * ur - xi[q] * ui;
-          const double x_i = xr[q] * ui + xi[q] * ur;
+        for (int q = 0; q < R; ++q) {
+          // x = G^-1 e_r for this group's row r; lane m holds x[col]
+          double x_r, x_i;
+          replay_unit<GROUP, NMAX>(ar, ai, piv, uniform(p.grp_fr[g + q] & 0xff), n, m, ur, ui,
+                                   x_r, x_i);
           const int gg = g + q;
           const int c_begin = uniform(p.grp_ptr[gg]);
           const int c_end = uniform(p.grp_ptr[gg + 1]);
@@ -414,6 +449,21 @@ __global__ __launch_bounds__(kWideBlock) void contract_wide_kernel(ContractArgs 
 }
 
 template <int GROUP, int NMAX, bool TREE, int MODE>
+__global__ __launch_bounds__(kWideBlock) void contract_wide_kernel(ContractArgs a) {
+  extern __shared__ double2 smem[];
+  wide_tile<GROUP, NMAX, TREE, MODE>(a, blockIdx.y, blockIdx.x, smem);
+}
+
+template <int GROUP, int NMAX, bool TREE, int MODE>
+__global__ __launch_bounds__(kWideBlock) void batch_wide_kernel(BatchArgs b) {
+  extern __shared__ double2 smem[];
+  for (int i = blockIdx.x; i < b.n_tiles; i += gridDim.x) {
+    const int4 tl = b.tiles[i];
+    wide_tile<GROUP, NMAX, TREE, MODE>(b.jobs[tl.x], tl.y, tl.z, smem);
+  }
+}
+
+template <int GROUP, int NMAX, bool TREE, int MODE>
 static hipError_t launch_wide_one(const ContractArgs& a, hipStream_t s) {
   dim3 grid(a.n_blk_t, a.T);
   const size_t lds = (size_t)a.plan.M * a.plan.M * sizeof(double2);
@@ -436,6 +486,43 @@ static hipError_t launch_wide_n(const ContractArgs& a, bool tree, bool diag, hip
 }
 
 int wide_sinks_per_wave(int nmax) { return nmax <= 16 ? kWave / 16 : kWave / 32; }
+
+template <int GROUP, int NMAX, bool TREE, int MODE>
+static hipError_t launch_batch_wide_m(const BatchArgs& b, int grid, size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&batch_wide_kernel<GROUP, NMAX, TREE, MODE>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((batch_wide_kernel<GROUP, NMAX, TREE, MODE>), dim3(grid), dim3(kWideBlock),
+                     lds, s, b);
+  return hipGetLastError();
+}
+
+template <int GROUP, int NMAX>
+static hipError_t launch_batch_wide_n(const BatchArgs& b, bool tree, bool with_a, int grid,
+                                      size_t lds, hipStream_t s) {
+  if (tree)
+    return with_a ? launch_batch_wide_m<GROUP, NMAX, true, 1>(b, grid, lds, s)
+                  : launch_batch_wide_m<GROUP, NMAX, true, 0>(b, grid, lds, s);
+  return with_a ? launch_batch_wide_m<GROUP, NMAX, false, 1>(b, grid, lds, s)
+                : launch_batch_wide_m<GROUP, NMAX, false, 0>(b, grid, lds, s);
+}
+
+int wide_bucket(int nmax) { return nmax <= 8 ? 8 : nmax <= 12 ? 12 : nmax <= 16 ? 16 : 24; }
+
+hipError_t launch_batch_wide(const BatchArgs& b, int nmax, bool tree, bool with_a, int grid,
+                             size_t lds, hipStream_t s) {
+  switch (wide_bucket(nmax)) {
+    case 8:
+      return launch_batch_wide_n<16, 8>(b, tree, with_a, grid, lds, s);
+    case 12:
+      return launch_batch_wide_n<16, 12>(b, tree, with_a, grid, lds, s);
+    case 16:
+      return launch_batch_wide_n<16, 16>(b, tree, with_a, grid, lds, s);
+    default:
+      return launch_batch_wide_n<32, 24>(b, tree, with_a, grid, lds, s);
+  }
+}
 
 hipError_t launch_contract_wide(const ContractArgs& a, int nmax, bool tree, bool diag,
                                 double2* C, double* A, hipStream_t s) {

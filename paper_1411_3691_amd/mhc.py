@@ -222,6 +222,85 @@ def contract_backward(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: t
     return gS, g_src, g_snk
 
 
+KERNELS = {"auto": _lib.SCHED_AUTO, "lane": _lib.SCHED_LANE, "group": _lib.SCHED_GROUP}
+
+
+class Batch:
+    """Many independent contractions in one captured graph.
+
+        batch = Batch(plans, T=[...], method="tree")
+        batch.run(S_list, w_src_list, w_snk_list, C_list)   # torch's stream
+
+    ``schedule`` = dict(kernel="auto"|"lane"|"group", blocks_per_cu=0,
+    items_per_tile=0) (0 = the library's choice).  Plans must stay alive as
+    long as the batch; the batch keeps references to them.
+    """
+
+    def __init__(self, plans, T, method: str = "tree", schedule: dict | None = None):
+        plans = list(plans)
+        T = np.ascontiguousarray(np.asarray(T), dtype=np.int32)
+        if len(plans) == 0 or T.shape != (len(plans),):
+            raise ValueError("need one slice count per plan")
+        self.plans = plans
+        self.T = [int(v) for v in T]
+        self.method = method
+        sc = dict(kernel="auto", blocks_per_cu=0, items_per_tile=0)
+        sc.update(schedule or {})
+        self.schedule = sc
+        cs = _lib.Schedule(KERNELS[sc["kernel"]], int(sc["blocks_per_cu"]),
+                           int(sc["items_per_tile"]))
+        arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+        h = ctypes.c_void_p()
+        check(lib().mhc_batch_create(arr, _i32p(T), len(plans), METHODS[method],
+                                     ctypes.byref(cs), ctypes.byref(h)))
+        self._h = h
+        self._destroy = lib().mhc_batch_destroy
+        self.device = plans[0].device
+
+    def __len__(self):
+        return len(self.plans)
+
+    def info(self) -> dict:
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        check(lib().mhc_batch_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(n_tiles=a.value, n_kernels=b.value, n_pairs=int(c.value))
+
+    def run(self, S, w_src, w_snk, C, A=None) -> None:
+        """Enqueue every job on torch's current stream: C[j] (and A[j]) of
+        job j from S[j], w_src[j], w_snk[j]."""
+        n = len(self.plans)
+        if not (len(S) == len(w_src) == len(w_snk) == len(C) == n) or \
+                (A is not None and len(A) != n):
+            raise ValueError(f"need {n} tensors per argument")
+        for j, pl in enumerate(self.plans):
+            T, dev = self.T[j], self.device
+            _check_dev(S[j], torch.complex128, (T, pl.M, pl.M), f"S[{j}]", dev)
+            _check_dev(w_src[j], torch.float64, (pl.n_src,), f"w_src[{j}]", dev)
+            _check_dev(w_snk[j], torch.float64, (pl.n_snk,), f"w_snk[{j}]", dev)
+            _check_dev(C[j], torch.complex128, (T,), f"C[{j}]", dev)
+            if A is not None:
+                _check_dev(A[j], torch.float64, (T,), f"A[{j}]", dev)
+
+        def ptrs(xs):
+            return (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+
+        check(lib().mhc_batch_run(self._h, ptrs(S), ptrs(w_src), ptrs(w_snk), ptrs(C),
+                                  ptrs(A) if A is not None else None, _stream_ptr()))
+
+    def __call__(self, S, w_src, w_snk, with_scale: bool = False):
+        C = [torch.empty(T, dtype=torch.complex128, device=self.device) for T in self.T]
+        A = ([torch.empty(T, dtype=torch.float64, device=self.device) for T in self.T]
+             if with_scale else None)
+        self.run(S, w_src, w_snk, C, A)
+        return (C, A) if with_scale else C
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._destroy(h)
+            self._h = None
+
+
 class Contract(torch.autograd.Function):
     """C = Contract.apply(plan, S, w_src, w_snk, method): differentiable in S
     and both weight arrays; the backward pass is the library's adjoint."""

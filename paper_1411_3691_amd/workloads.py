@@ -198,3 +198,47 @@ def random_pairs(rng, T: int, n_src: int, n_snk: int, count: int) -> np.ndarray:
 
 def log_uniform_int(rng, lo: int, hi: int) -> int:
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+# Batched uneven jobs: 256 independent correlators.  Per job, each flavour's
+# block size is drawn from U{2..18} independently, the term count per side
+# from round(exp(U[ln 50, ln 5000])), the slice count from U{8..64} and the
+# number of sites from {2, 4, 8} (M = 12 x sites); terms are single-
+# substitution forests with branching 8 and depth <= 4; S is N(0,1)+iN(0,1)
+# without decay.  Every job's shape is drawn first from one generator, so a
+# subset of jobs has the same shapes as in the full batch.
+BATCH_SEED_K = 4
+BATCH_JOBS = 256
+
+
+def batch_shapes(n_jobs: int = BATCH_JOBS) -> list[dict]:
+    rng = rng_for(BATCH_SEED_K, 0)
+    out = []
+    for _ in range(n_jobs):
+        nf = (int(rng.integers(2, 19)), int(rng.integers(2, 19)))
+        n_src = log_uniform_int(rng, 50, 5000)
+        n_snk = log_uniform_int(rng, 50, 5000)
+        T = int(rng.integers(8, 65))
+        sites = int(rng.choice([2, 4, 8]))
+        out.append(dict(nf=nf, n_src=n_src, n_snk=n_snk, T=T, M=12 * sites))
+    return out
+
+
+def batch_job(j: int, shape: dict | None = None, **over) -> Workload:
+    """Job ``j`` of the batched workload (its own seeds); keyword overrides
+    shrink it for tests (e.g. ``T=2, n_src=100``)."""
+    cfg = dict(batch_shapes(j + 1)[j] if shape is None else shape)
+    cfg.update(over)
+    nf = tuple(int(n) for n in cfg["nf"])
+
+    def g(stream):
+        return np.random.Generator(np.random.PCG64(
+            np.random.SeedSequence([SEED_BASE, BATCH_SEED_K, j, stream])))
+
+    S = make_propagator(g(0), cfg["T"], cfg["M"], 0.0)
+    src = make_tree_terms(g(1), cfg["n_src"], cfg["M"], nf, 8, 4)
+    snk = make_tree_terms(g(2), cfg["n_snk"], cfg["M"], nf, 8, 4)
+    w_src = g(3).standard_normal(cfg["n_src"])
+    w_snk = g(4).standard_normal(cfg["n_snk"])
+    full = dict(cfg, k=BATCH_SEED_K, terms="tree", branching=8, depth=4, decay=0.0, job=j)
+    return Workload(f"batch[{j}]", S, src, snk, w_src, w_snk, nf, full)

@@ -1,0 +1,141 @@
+"""GPU batched jobs: many independent correlators with uneven flavour blocks,
+term counts and slice counts in one captured graph, against the CPU oracle
+and against the same jobs run one at a time."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import contract as oc
+from paper_1411_3691_amd import mhc
+from paper_1411_3691_amd import workloads as W
+from paper_1411_3691_amd._lib import MhcError
+from parity_util import check_C
+
+pytestmark = pytest.mark.gpu
+
+
+def upload(ws):
+    plans, S, a, b = [], [], [], []
+    for w in ws:
+        plans.append(mhc.Plan(mhc.Tree(mhc.Terms(w.src, w.nf, w.M)), mhc.Terms(w.snk, w.nf, w.M)))
+        dev = plans[-1].device
+        S.append(torch.from_numpy(w.S).to(dev))
+        a.append(torch.from_numpy(w.w_src).to(dev))
+        b.append(torch.from_numpy(w.w_snk).to(dev))
+    return plans, S, a, b
+
+
+def small_jobs():
+    # eight jobs of the batched workload cut to oracle-sized pieces (2-3
+    # slices, <= 150 x 60 terms; their own flavour blocks and M), plus two
+    # jobs with equal blocks <= 8 that take the one-matrix-per-lane kernel
+    sh = W.batch_shapes(8)
+    ws = [W.batch_job(j, sh[j], T=2 + j % 2, n_src=min(150, sh[j]["n_src"]),
+                      n_snk=min(60, sh[j]["n_snk"])) for j in range(8)]
+    ws.append(W.batch_job(300, dict(nf=(4, 4), n_src=140, n_snk=70, T=3, M=24)))
+    ws.append(W.batch_job(301, dict(nf=(7, 7), n_src=90, n_snk=65, T=2, M=48)))
+    return ws
+
+
+def cpu(xs):
+    return [x.cpu().numpy() for x in xs]
+
+
+@pytest.mark.parametrize("method", ["plain", "tree"])
+def test_batch_matches_oracle(method):
+    ws = small_jobs()
+    plans, S, a, b = upload(ws)
+    batch = mhc.Batch(plans, [w.T for w in ws], method)
+    C, A = batch(S, a, b, with_scale=True)
+    torch.cuda.synchronize()
+    info = batch.info()
+    assert info["n_pairs"] == sum(w.n_pairs for w in ws)
+    assert info["n_kernels"] >= 3          # lane kernels, group kernels, reduction
+    for w, c, s in zip(ws, cpu(C), cpu(A)):
+        Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+        check_C(c, s, Cw, Aw)
+
+
+def test_full_size_smallest_jobs_against_oracle():
+    # the four cheapest jobs of the 256-job workload at their full shapes
+    sh = W.batch_shapes()
+    order = sorted(range(len(sh)), key=lambda j: sh[j]["T"] * sh[j]["n_src"] * sh[j]["n_snk"])
+    ws = [W.batch_job(j, sh[j]) for j in order[:4]]
+    plans, S, a, b = upload(ws)
+    C, A = mhc.Batch(plans, [w.T for w in ws], "tree")(S, a, b, with_scale=True)
+    torch.cuda.synchronize()
+    for w, c, s in zip(ws, cpu(C), cpu(A)):
+        Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+        check_C(c, s, Cw, Aw)
+
+
+def test_batch_equals_jobs_run_alone():
+    ws = small_jobs()
+    plans, S, a, b = upload(ws)
+    for method in ("plain", "tree"):
+        C, A = mhc.Batch(plans, [w.T for w in ws], method)(S, a, b, with_scale=True)
+        for j, pl in enumerate(plans):
+            c1, a1 = mhc.contract(pl, S[j], a[j], b[j], method, with_scale=True)
+            # same kernels, chunked differently: equal up to summation order
+            assert torch.all(torch.abs(C[j] - c1) <= 1e-12 * a1), (method, j)
+            assert torch.allclose(A[j], a1, rtol=1e-12, atol=0)
+
+
+def test_graph_replays_and_new_buffers():
+    ws = small_jobs()
+    plans, S, a, b = upload(ws)
+    batch = mhc.Batch(plans, [w.T for w in ws], "tree")
+    C0 = cpu(batch(S, a, b))
+    # replays with the program's own eager work and synchronisations between
+    # them: every replay equals the first bit for bit
+    for r in range(4):
+        x = torch.randn(256, 256, dtype=torch.float64, device=plans[0].device)
+        y = (x @ x).sum()
+        torch.cuda.synchronize()
+        C = [torch.full((w.T,), complex(r, -r), dtype=torch.complex128, device=plans[0].device)
+             for w in ws] if r % 2 else None
+        if C is None:
+            Cr = cpu(batch(S, a, b))        # new output buffers each call
+        else:
+            batch.run(S, a, b, C)
+            Cr = cpu(C)
+        del y
+        for j in range(len(ws)):
+            assert Cr[j].tobytes() == C0[j].tobytes(), (r, j)
+    # the graph reads the inputs at replay time: doubling S_t (exact in
+    # binary) multiplies every determinant product by 2^(sum of block sizes)
+    for s in S:
+        s.mul_(2.0)
+    C2 = cpu(batch(S, a, b))
+    for j, w in enumerate(ws):
+        assert C2[j].tobytes() == (C0[j] * 2.0 ** sum(w.nf)).tobytes(), j
+
+
+@pytest.mark.parametrize("sched", [
+    dict(kernel="group"),
+    dict(kernel="auto", blocks_per_cu=1, items_per_tile=7),
+    dict(kernel="auto", blocks_per_cu=4, items_per_tile=500),
+])
+def test_schedules_agree(sched):
+    ws = small_jobs()
+    plans, S, a, b = upload(ws)
+    ref_C, ref_A = mhc.Batch(plans, [w.T for w in ws], "tree")(S, a, b, with_scale=True)
+    C = mhc.Batch(plans, [w.T for w in ws], "tree", sched)(S, a, b)
+    for j in range(len(ws)):
+        assert torch.all(torch.abs(C[j] - ref_C[j]) <= 1e-12 * ref_A[j]), j
+
+
+def test_lane_schedule_refuses_uneven_jobs():
+    ws = small_jobs()
+    plans, S, a, b = upload(ws)
+    with pytest.raises(MhcError, match="MHC_E_UNSUPPORTED"):
+        mhc.Batch(plans, [w.T for w in ws], "tree", dict(kernel="lane"))
+    # equal blocks <= 8 only: accepted, and equal to the automatic choice
+    C = mhc.Batch(plans[-2:], [w.T for w in ws[-2:]], "tree", dict(kernel="lane"))(
+        S[-2:], a[-2:], b[-2:])
+    R, RA = mhc.Batch(plans[-2:], [w.T for w in ws[-2:]], "tree")(S[-2:], a[-2:], b[-2:],
+                                                                 with_scale=True)
+    for j in range(2):
+        assert torch.all(torch.abs(C[j] - R[j]) <= 1e-12 * RA[j])
+    with pytest.raises(ValueError):
+        mhc.Batch(plans, [w.T for w in ws], "tree")(S[:-1] + [S[0]], a, b)

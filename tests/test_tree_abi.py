@@ -152,6 +152,27 @@ def test_null_handles_and_destroy():
     assert b"policy" in L.mhc_last_error()
 
 
+def test_batch_argument_errors_before_device_work():
+    L = _lib.lib()
+    L.mhc_batch_destroy(None)
+    h = ctypes.c_void_p()
+    plans = (ctypes.c_void_p * 1)(None)
+    T = np.array([4], dtype=np.int32)
+    Tp = T.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    assert L.mhc_batch_create(None, Tp, 1, 1, None, ctypes.byref(h)) == -1
+    assert L.mhc_batch_create(plans, Tp, 0, 1, None, ctypes.byref(h)) == -1
+    assert L.mhc_batch_create(plans, Tp, 1, 1, None, None) == -1
+    assert L.mhc_batch_create(plans, Tp, 1, 5, None, ctypes.byref(h)) == -1
+    assert b"method" in L.mhc_last_error()
+    for bad in ((3, 0, 0), (0, 9, 0), (0, -1, 0), (0, 0, -4)):
+        sc = _lib.Schedule(*bad)
+        assert L.mhc_batch_create(plans, Tp, 1, 1, ctypes.byref(sc), ctypes.byref(h)) == -1
+        assert b"schedule" in L.mhc_last_error()
+    assert not h.value
+    assert L.mhc_batch_run(None, None, None, None, None, None, None) == -1
+    assert L.mhc_batch_info(None, None, None, None) == -1
+
+
 def test_plan_shape_mismatch_is_reported_before_device_work():
     # differing M or flavour structure between source and sink terms
     src = mhc.Terms([[0, 1, 2]], (2, 1), 10)
