@@ -64,7 +64,11 @@ enum { MHC_GREEDY_R1 = 1, MHC_GREEDY_R2 = 2 };
 /* Contraction methods. */
 enum {
   MHC_PLAIN_LU = 0,    /* pivoted LU of every pair and flavour block (Sec. 2) */
-  MHC_UPDATE_TREE = 1  /* dominator LU + rank-1 updates (Secs. 2-3)           */
+  MHC_UPDATE_TREE = 1, /* dominator LU + rank-1 updates (Secs. 2-3)          */
+  MHC_UPDATE_TREE2 = 2 /* source and sink trees: one LU per (source dominator,
+                        * sink dominator), rank-1 row and column updates and
+                        * the rank-2 form for pairs changed on both sides;
+                        * needs mhc_plan_attach_sink_tree                    */
 };
 
 typedef struct mhc_terms mhc_terms;
@@ -178,6 +182,18 @@ mhc_status mhc_contract_backward(mhc_plan* plan, int32_t T, const void* S,
  *                    the adjoint skipped. */
 mhc_status mhc_plan_status(mhc_plan* plan, int64_t* n_fallback,
                            int64_t* n_singular_grad);
+
+/* Attaches an update tree over the plan's sink terms (built by
+ * mhc_tree_build on sink terms equal to the ones the plan was created with)
+ * for method MHC_UPDATE_TREE2.  Sec. 3 links terms that differ in one row
+ * or one column but uses rows only; the sink tree adds the columns.  The
+ * tree's tables are copied to the device (synchronously on `stream`); a
+ * tree attached before is replaced (after waiting for the device).  With
+ * MHC_UPDATE_TREE2, mhc_contract needs A == NULL and pair_det == NULL.
+ * Errors: MHC_E_ARG (NULL handle), MHC_E_SHAPE (other sink terms),
+ * MHC_E_UNSUPPORTED (blocks not all of one size n <= 8), MHC_E_DEVICE,
+ * MHC_E_OOM. */
+mhc_status mhc_plan_attach_sink_tree(mhc_plan* plan, const mhc_tree* snk_tree, void* stream);
 
 /* Batched jobs.  Many independent contractions (each a plan, its number of
  * slices and its own buffers) run as one captured graph: one persistent

@@ -24,6 +24,7 @@ GREEDY_R1 = 1
 GREEDY_R2 = 2
 PLAIN_LU = 0
 UPDATE_TREE = 1
+UPDATE_TREE2 = 2
 SCHED_AUTO = 0
 SCHED_LANE = 1
 SCHED_GROUP = 2
@@ -58,6 +59,7 @@ SIGNATURES = {
     "mhc_contract": (_I32, [_P, _I32, _I32, _P, _PD, _PD, _P, _PD, _P, _P]),
     "mhc_contract_backward": (_I32, [_P, _I32, _P, _PD, _PD, _P, _P, _PD, _PD, _P]),
     "mhc_plan_status": (_I32, [_P, _PI64, _PI64]),
+    "mhc_plan_attach_sink_tree": (_I32, [_P, _P, _P]),
     "mhc_batch_create": (_I32, [ctypes.POINTER(_P), _PI32, _I32, _I32, ctypes.POINTER(Schedule),
                                 ctypes.POINTER(_P)]),
     "mhc_batch_run": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),

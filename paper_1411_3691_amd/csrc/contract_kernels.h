@@ -26,8 +26,24 @@ struct PlanView {
   const uint32_t* snk_coloff;     // [sn][n_snk_pad] byte offset b*16
 };
 
+// Sink-side update tree (two-sided contraction).  Sink dominators are
+// stored in processing order (sorted so that the lanes of a wave have
+// similar numbers of groups and children); lanes past n_sdom are padding
+// with no groups.  Groups of a dominator are sorted by (flavour, column).
+struct SinkTreeView {
+  int n_sdom, n_sdom_pad;
+  const int32_t* sdom_term;       // [n_sdom_pad] sink term id
+  const uint32_t* sdom_coloff;    // [sn][n_sdom_pad] column byte offsets
+  const int32_t* sdom_grp;        // [n_sdom_pad + 1] group range
+  const int32_t* sgrp_fc;         // [n_sgroups] (flavour << 8) | column
+  const int32_t* sgrp_ptr;        // [n_sgroups + 1] child range
+  const uint32_t* schild_coloff;  // [n_schildren] new column byte offset
+  const int32_t* schild_term;     // [n_schildren] sink term id
+};
+
 struct ContractArgs {
   PlanView plan;
+  SinkTreeView snk;               // used by the two-sided contraction only
   const double2* S;               // [T][M][M]
   const double* w_src;            // [n_src]
   const double* w_snk;            // [n_snk]
@@ -63,6 +79,10 @@ hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag,
 hipError_t launch_contract_wide(const ContractArgs& a, int nmax, bool tree, bool diag,
                                 double2* C, double* A, hipStream_t s);
 int wide_sinks_per_wave(int nmax);
+
+// Two-sided update trees (one matrix per lane, every block of size n <= 8):
+// work items are (source dominator, block of 64 sink dominators).
+hipError_t launch_contract_two_sided(const ContractArgs& a, int n, double2* C, hipStream_t s);
 
 // Final fixed-order reduction of the workgroup partials into C (and A).
 hipError_t launch_reduce(const ContractArgs& a, double2* C, double* A, hipStream_t s);

@@ -35,6 +35,11 @@ struct mhc_plan {
   // adjoint scratch (grown on demand)
   void* adj_scratch = nullptr;
   size_t adj_cap = 0;
+  // sink terms (host copy) and the attached sink tree, if any
+  std::vector<int32_t> snk_idx;
+  void* dev_tree2 = nullptr;
+  mhc::kern::SinkTreeView view_snk{};
+  int32_t n_sdom = 0, n_sgroups = 0, n_schildren = 0;
 };
 
 namespace {
@@ -101,6 +106,7 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   pl->n_dom = (int32_t)tree->dom_order.size();
   pl->n_groups = (int32_t)tree->grp_f.size();
   pl->n_children = (int32_t)tree->grp_child.size();
+  pl->snk_idx = snk->idx;
 
   const int sn = src.sn;
   const uint32_t row_bytes = (uint32_t)src.M * 16u;
@@ -194,9 +200,108 @@ void mhc_plan_destroy(mhc_plan* pl) {
   hipDeviceSynchronize();
   if (pl->partial) hipFree(pl->partial);
   if (pl->adj_scratch) hipFree(pl->adj_scratch);
+  if (pl->dev_tree2) hipFree(pl->dev_tree2);
   if (pl->dev_tables) hipFree(pl->dev_tables);
   hipSetDevice(cur);
   delete pl;
+}
+
+mhc_status mhc_plan_attach_sink_tree(mhc_plan* pl, const mhc_tree* st, void* stream) {
+  if (!pl || !st) return fail(MHC_E_ARG, "mhc_plan_attach_sink_tree: NULL handle");
+  const mhc_terms& t = st->terms;
+  if (t.n_terms != pl->n_snk || t.sn != pl->sn || t.M != pl->M || t.off != pl->off ||
+      t.idx != pl->snk_idx)
+    return fail(MHC_E_SHAPE,
+                "mhc_plan_attach_sink_tree: the tree is not built on the plan's sink terms");
+  if (!pl->uniform_n || pl->n > 8)
+    return fail(MHC_E_UNSUPPORTED,
+                "mhc_plan_attach_sink_tree: two-sided trees need every flavour block of "
+                "size n <= 8");
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "mhc_plan_attach_sink_tree/hipGetDevice");
+  if (cur != pl->device)
+    return fail(MHC_E_DEVICE, "mhc_plan_attach_sink_tree: current device differs from "
+                              "the plan's device");
+  const int nd = (int)st->dom_order.size();
+  // processing order: most children first, then most groups, then tree order
+  std::vector<int32_t> order(nd);
+  for (int k = 0; k < nd; ++k) order[k] = k;
+  auto n_children = [&](int k) {
+    return st->grp_ptr[st->dom_grp[k + 1]] - st->grp_ptr[st->dom_grp[k]];
+  };
+  auto n_groups = [&](int k) { return st->dom_grp[k + 1] - st->dom_grp[k]; };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (n_children(x) != n_children(y)) return n_children(x) > n_children(y);
+    return n_groups(x) > n_groups(y);
+  });
+  const int pad = (nd + kSinkBlock - 1) / kSinkBlock * kSinkBlock;
+  const int sn = pl->sn;
+  std::vector<int32_t> sdom_term(pad), sdom_grp(pad + 1), sgrp_fc, sgrp_ptr(1, 0), schild_term;
+  std::vector<uint32_t> sdom_coloff((size_t)sn * pad), schild_coloff;
+  for (int k = 0; k < pad; ++k) {
+    const int kk = k < nd ? order[k] : order[0];
+    const int term = st->dom_order[kk];
+    sdom_term[k] = term;
+    for (int q = 0; q < sn; ++q)
+      sdom_coloff[(size_t)q * pad + k] = (uint32_t)t.idx[(size_t)term * sn + q] * 16u;
+    sdom_grp[k] = (int32_t)sgrp_fc.size();
+    if (k >= nd) continue;
+    for (int g = st->dom_grp[kk]; g < st->dom_grp[kk + 1]; ++g) {
+      const int f = st->grp_f[g], c = st->grp_r[g];
+      sgrp_fc.push_back((f << 8) | c);
+      for (int ci = st->grp_ptr[g]; ci < st->grp_ptr[g + 1]; ++ci) {
+        const int u = st->grp_child[ci];
+        schild_term.push_back(u);
+        schild_coloff.push_back((uint32_t)t.idx[(size_t)u * sn + t.off[f] + c] * 16u);
+      }
+      sgrp_ptr.push_back((int32_t)schild_term.size());
+    }
+  }
+  sdom_grp[pad] = (int32_t)sgrp_fc.size();
+  std::vector<char> img;
+  const size_t o_term = append(img, sdom_term);
+  const size_t o_coloff = append(img, sdom_coloff);
+  const size_t o_grp = append(img, sdom_grp);
+  const size_t o_fc = append(img, sgrp_fc);
+  const size_t o_ptr = append(img, sgrp_ptr);
+  const size_t o_ccol = append(img, schild_coloff);
+  const size_t o_cterm = append(img, schild_term);
+  void* dev = nullptr;
+  e = hipMalloc(&dev, img.size());
+  if (e != hipSuccess) return fail(MHC_E_OOM, "mhc_plan_attach_sink_tree: device tables");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  e = hipMemcpyAsync(dev, img.data(), img.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    hipFree(dev);
+    return hip_fail(e, "mhc_plan_attach_sink_tree/upload");
+  }
+  if (pl->dev_tree2) {
+    // a previous sink tree may still be read by queued work
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      hipFree(dev);
+      return hip_fail(e, "mhc_plan_attach_sink_tree/sync");
+    }
+    hipFree(pl->dev_tree2);
+  }
+  pl->dev_tree2 = dev;
+  char* base = static_cast<char*>(dev);
+  mhc::kern::SinkTreeView& v = pl->view_snk;
+  v.n_sdom = nd;
+  v.n_sdom_pad = pad;
+  v.sdom_term = reinterpret_cast<const int32_t*>(base + o_term);
+  v.sdom_coloff = reinterpret_cast<const uint32_t*>(base + o_coloff);
+  v.sdom_grp = reinterpret_cast<const int32_t*>(base + o_grp);
+  v.sgrp_fc = reinterpret_cast<const int32_t*>(base + o_fc);
+  v.sgrp_ptr = reinterpret_cast<const int32_t*>(base + o_ptr);
+  v.schild_coloff = reinterpret_cast<const uint32_t*>(base + o_ccol);
+  v.schild_term = reinterpret_cast<const int32_t*>(base + o_cterm);
+  pl->n_sdom = nd;
+  pl->n_sgroups = (int32_t)sgrp_fc.size();
+  pl->n_schildren = (int32_t)schild_term.size();
+  return MHC_OK;
 }
 
 mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
@@ -207,8 +312,15 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
     return fail(MHC_E_ARG, "mhc_contract: NULL buffer");
   if (T < 1) return fail(MHC_E_ARG, "mhc_contract: T < 1");
   if (T > 65535) return fail(MHC_E_ARG, "mhc_contract: T > 65535");
-  if (method != MHC_PLAIN_LU && method != MHC_UPDATE_TREE)
+  if (method != MHC_PLAIN_LU && method != MHC_UPDATE_TREE && method != MHC_UPDATE_TREE2)
     return fail(MHC_E_ARG, "mhc_contract: unknown method");
+  if (method == MHC_UPDATE_TREE2) {
+    if (!pl->dev_tree2)
+      return fail(MHC_E_STATE, "mhc_contract: no sink tree attached to the plan");
+    if (A || pair_det)
+      return fail(MHC_E_UNSUPPORTED,
+                  "mhc_contract: the two-sided method computes neither A nor pair dets");
+  }
   int cur = -1;
   hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e, "mhc_contract/hipGetDevice");
@@ -218,6 +330,7 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   if (pair_det && pl->F > 4)
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_contract: pair_det output supports at most 4 flavour blocks");
+  const bool two = method == MHC_UPDATE_TREE2;
   const bool tree = method == MHC_UPDATE_TREE;
   const bool diag = A != nullptr || pair_det != nullptr;
   // one matrix per lane when every block has the same size n <= 8, else one
@@ -225,8 +338,9 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   const bool narrow = pl->uniform_n && pl->n <= 8;
   const int sinks_per_item = narrow ? kSinkBlock : mhc::kern::wide_sinks_per_wave(pl->n);
   const int waves_per_block = narrow ? 4 : 8;
-  const int rowsets = tree ? pl->n_dom : pl->n_src;
-  const int n_sblk = (pl->n_snk + sinks_per_item - 1) / sinks_per_item;
+  const int rowsets = (tree || two) ? pl->n_dom : pl->n_src;
+  const int n_sblk = two ? pl->view_snk.n_sdom_pad / kSinkBlock
+                         : (pl->n_snk + sinks_per_item - 1) / sinks_per_item;
   const long long n_items = (long long)rowsets * n_sblk;
   if (n_items > 0x7fffffffLL)
     return fail(MHC_E_UNSUPPORTED, "mhc_contract: too many work items");
@@ -260,7 +374,11 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   a.n_items = (int)n_items;
   a.n_blk_t = n_blk_t;
   a.n_sblk = n_sblk;
-  if (narrow)
+  a.snk = pl->view_snk;
+  if (two)
+    e = mhc::kern::launch_contract_two_sided(a, pl->n, static_cast<double2*>(C),
+                                             reinterpret_cast<hipStream_t>(stream));
+  else if (narrow)
     e = mhc::kern::launch_contract(a, pl->n, tree, diag, static_cast<double2*>(C), A,
                                    reinterpret_cast<hipStream_t>(stream));
   else

@@ -1,0 +1,386 @@
+// Two-sided update trees (gfx950): source and sink terms both in dominating
+// sets, one pivoted LU per (source dominator, sink dominator, flavour).
+//
+// The paper's graph links matrices that differ in a single row or column
+// (Sec. 3) but builds it over source terms only; here the sink terms get
+// their own tree as well.  With G the dominators' block, x_r = G^-1 e_r and
+// y_c = e_c^T G^-1, the pairs of one (source partition, sink partition)
+// have the determinant ratios (matrix determinant lemma, Sec. 2)
+//   source child (row r -> new row s):      rho   = s . x_r
+//   sink child (column c -> new column v):  sigma = y_c . v
+//   both, in different flavour blocks:      rho * sigma
+//   both, in the same block:                tau = rho * sigma - kappa (beta - alpha)
+// where kappa = (G^-1)[c][r], beta = s^T G^-1 v and alpha = S[new row][new
+// column]; tau is the rank-2 form of the lemma (det(I + V^T G^-1 U) for the
+// two changes).  The weighted sum of every pair of the two partitions is
+//   prod_f det G_f * ((w_a + sum_c w_c rho_c) (w_b + sum_d w_d sigma_d)
+//                     - sum over same-block (c, d) of w_c w_d kappa (beta - alpha)).
+//
+// Work decomposition: a wave holds one source dominator (wave-uniform
+// source tree, as in the one-sided kernel) and 64 sink dominators, one per
+// lane, each with its own sink groups and children (per-lane loops; the
+// sink dominators are sorted so that neighbouring lanes have similar
+// counts).  Source children's row vectors z_c = s_c^T G^-1 are solved only
+// in flavours where some lane of the wave has sink children.
+//
+// A lane whose dominator block has an exactly zero pivot evaluates every
+// pair of its two partitions by direct LU instead (counted in the plan's
+// fallback counter).
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "contract_kernels.h"
+#include "lu_device.h"
+
+namespace mhc {
+namespace kern {
+
+// b with h^T G^-1 = b^T P (that is (h^T G^-1)[perm[m]] = b[m]) from the
+// factors of lu<N, true> (P G = L U, diagonal holding 1/U_mm): a^T U = h^T,
+// then b^T L = a^T.  (br, bi) holds h on entry.
+template <int N>
+__device__ __forceinline__ void solve_row(const double (&gr)[N][N], const double (&gi)[N][N],
+                                          double (&br)[N], double (&bi)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double tr = br[j], ti = bi[j];
+#pragma unroll
+    for (int i = 0; i < j; ++i) {
+      tr = tr - br[i] * gr[i][j] + bi[i] * gi[i][j];
+      ti = ti - br[i] * gi[i][j] - bi[i] * gr[i][j];
+    }
+    br[j] = tr * gr[j][j] - ti * gi[j][j];
+    bi[j] = tr * gi[j][j] + ti * gr[j][j];
+  }
+#pragma unroll
+  for (int j = N - 2; j >= 0; --j) {
+    double tr = br[j], ti = bi[j];
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      tr = tr - br[i] * gr[i][j] + bi[i] * gi[i][j];
+      ti = ti - br[i] * gi[i][j] - bi[i] * gr[i][j];
+    }
+    br[j] = tr;
+    bi[j] = ti;
+  }
+}
+
+// sum_m b[m] S_t[prow[m]][col]: a row solution against a sink column.
+template <int N>
+__device__ __forceinline__ void dot_col(const char* lds, const uint32_t (&prow)[N], uint32_t col,
+                                        const double (&br)[N], const double (&bi)[N],
+                                        double& re, double& im) {
+  re = 0.0;
+  im = 0.0;
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const double2 v = *reinterpret_cast<const double2*>(lds + prow[m] + col);
+    re += br[m] * v.x - bi[m] * v.y;
+    im += br[m] * v.y + bi[m] * v.x;
+  }
+}
+
+// det of one flavour block with source row r replaced by `newrow` (r < 0:
+// none) and sink column c replaced by `newcol` (c < 0: none), by direct LU.
+template <int N>
+__device__ __forceinline__ void block_det2(const char* lds, const uint32_t* rowoff, int r,
+                                           uint32_t newrow, const uint32_t (&co)[N], int c,
+                                           uint32_t newcol, double& dre, double& dim) {
+  uint32_t ro[N], cl[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) ro[m] = (m == r) ? newrow : rowoff[m];
+#pragma unroll
+  for (int m = 0; m < N; ++m) cl[m] = (m == c) ? newcol : co[m];
+  double gr[N][N], gi[N][N];
+  int perm[N];
+  bool z;
+  gather<N>(lds, ro, cl, gr, gi);
+  lu<N, false>(gr, gi, dre, dim, perm, z);
+}
+
+template <int N>
+__device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int chunk,
+                                               double2* smem) {
+  const PlanView& p = a.plan;
+  const SinkTreeView& q = a.snk;
+  __syncthreads();  // the previous tile of this workgroup is done with LDS
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = uniform(threadIdx.x / kWave);
+  const int MM = p.M * p.M;
+  const double2* St = a.S + (size_t)t * MM;
+  for (int e = threadIdx.x; e < MM; e += kBlock) smem[e] = St[e];
+  __syncthreads();
+  const char* lds = reinterpret_cast<const char*>(smem);
+
+  double acc_re = 0.0, acc_im = 0.0;
+  uint32_t n_fallback = 0;
+  const int F = p.F;
+  const int sn = p.sn;
+  const int pad = q.n_sdom_pad;
+
+  for (int item = chunk + a.n_blk_t * wave; item < a.n_items;
+       item += a.n_blk_t * kWavesPerBlock) {
+    const int d = uniform(item / a.n_sblk);
+    const int sb = uniform(item - d * a.n_sblk);
+    const int k = sb * kWave + lane;
+    const bool valid = k < q.n_sdom;
+    const int term_a = uniform(p.dom_term[d]);
+    const double wa = a.w_src[term_a];
+    const double wb = valid ? a.w_snk[q.sdom_term[k]] : 0.0;
+    const uint32_t* rowoff_d = p.dom_rowoff + (size_t)d * sn;
+    const int g_begin = uniform(p.dom_grp[d]);
+    const int g_end = uniform(p.dom_grp[d + 1]);
+    const int sg_begin = q.sdom_grp[k];
+    const int sg_end = q.sdom_grp[k + 1];
+
+    double Pre = 1.0, Pim = 0.0;     // prod_f det G_f
+    double Rre = 0.0, Rim = 0.0;     // sum_c w_c rho_c
+    double Sre = 0.0, Sim = 0.0;     // sum_d w_d sigma_d
+    double Kre = 0.0, Kim = 0.0;     // sum over same-block pairs
+    bool bad = false;
+    int g = g_begin;
+    int sg = sg_begin;
+    for (int f = 0; f < F; ++f) {
+      const int o = p.off[f];
+      uint32_t co[N], ro[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) co[c] = q.sdom_coloff[(size_t)(o + c) * pad + k];
+#pragma unroll
+      for (int m = 0; m < N; ++m) ro[m] = rowoff_d[o + m];
+      double gr[N][N], gi[N][N];
+      int perm[N];
+      bool zero;
+      double dre, dim;
+      gather<N>(lds, ro, co, gr, gi);
+      lu<N, true>(gr, gi, dre, dim, perm, zero);
+      bad = bad || zero;
+      {
+        const double tr = Pre * dre - Pim * dim;
+        Pim = Pre * dim + Pim * dre;
+        Pre = tr;
+      }
+      // row offset of the original row now at position m
+      uint32_t prow[N];
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        uint32_t v = ro[0];
+#pragma unroll
+        for (int j = 1; j < N; ++j)
+          if (perm[m] == j) v = ro[j];
+        prow[m] = v;
+      }
+      // this lane's sink groups in flavour f
+      int sg_f = sg;
+      while (sg_f < sg_end && (q.sgrp_fc[sg_f] >> 8) == f) ++sg_f;
+      for (int h = sg; h < sg_f; ++h) {
+        const int cc = q.sgrp_fc[h] & 0xff;
+        double br[N], bi[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          br[j] = (j == cc) ? 1.0 : 0.0;
+          bi[j] = 0.0;
+        }
+        solve_row<N>(gr, gi, br, bi);
+        for (int ch = q.sgrp_ptr[h]; ch < q.sgrp_ptr[h + 1]; ++ch) {
+          const double wd = a.w_snk[q.schild_term[ch]];
+          double sr, si;
+          dot_col<N>(lds, prow, q.schild_coloff[ch], br, bi, sr, si);
+          Sre += wd * sr;
+          Sim += wd * si;
+        }
+      }
+      // the source groups of flavour f (wave-uniform)
+      int g_f_end = g;
+      while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
+      const bool pairs = __builtin_amdgcn_ballot_w64(sg < sg_f) != 0;
+      for (int gg = g; gg < g_f_end; ++gg) {
+        const int r = uniform(p.grp_fr[gg] & 0xff);
+        double xr[N], xi[N];
+        solve_unit<N>(gr, gi, perm, r, xr, xi);
+        const int c_begin = uniform(p.grp_ptr[gg]);
+        const int c_end = uniform(p.grp_ptr[gg + 1]);
+        for (int c = c_begin; c < c_end; ++c) {
+          const uint32_t crow = uniform(p.child_rowoff[c]);
+          const double wc = a.w_src[uniform(p.child_term[c])];
+          double br[N], bi[N];
+          double rr = 0.0, ri = 0.0;
+#pragma unroll
+          for (int n = 0; n < N; ++n) {
+            const double2 s = *reinterpret_cast<const double2*>(lds + crow + co[n]);
+            br[n] = s.x;
+            bi[n] = s.y;
+            rr += s.x * xr[n] - s.y * xi[n];
+            ri += s.x * xi[n] + s.y * xr[n];
+          }
+          Rre += wc * rr;
+          Rim += wc * ri;
+          if (pairs) {
+            solve_row<N>(gr, gi, br, bi);   // z_c = s_c^T G^-1, as b^T P
+            for (int h = sg; h < sg_f; ++h) {
+              const int cc = q.sgrp_fc[h] & 0xff;
+              // kappa = (G^-1)[cc][r] = x_r[cc]
+              double kr = xr[0], ki = xi[0];
+#pragma unroll
+              for (int j = 1; j < N; ++j)
+                if (cc == j) {
+                  kr = xr[j];
+                  ki = xi[j];
+                }
+              double tre = 0.0, tim = 0.0;
+              for (int ch = q.sgrp_ptr[h]; ch < q.sgrp_ptr[h + 1]; ++ch) {
+                const uint32_t col = q.schild_coloff[ch];
+                const double wd = a.w_snk[q.schild_term[ch]];
+                double bre, bim;
+                dot_col<N>(lds, prow, col, br, bi, bre, bim);
+                const double2 al = *reinterpret_cast<const double2*>(lds + crow + col);
+                tre += wd * (bre - al.x);
+                tim += wd * (bim - al.y);
+              }
+              Kre += wc * (kr * tre - ki * tim);
+              Kim += wc * (kr * tim + ki * tre);
+            }
+          }
+        }
+      }
+      g = g_f_end;
+      sg = sg_f;
+    }
+
+    double vre, vim;
+    {
+      const double ar_ = wa + Rre, ai_ = Rim;
+      const double br_ = wb + Sre, bi_ = Sim;
+      const double mr = ar_ * br_ - ai_ * bi_ - Kre;
+      const double mi = ar_ * bi_ + ai_ * br_ - Kim;
+      vre = Pre * mr - Pim * mi;
+      vim = Pre * mi + Pim * mr;
+    }
+
+    // a dominator block with an exactly zero pivot: every pair of the two
+    // partitions by direct LU (source members wave-uniform, sink members
+    // per lane)
+    const bool need = valid && bad;
+    if (__builtin_amdgcn_ballot_w64(need) != 0) {
+      double fre = 0.0, fim = 0.0;
+      // source members: the dominator (ci = cs_begin - 1), then its children
+      const int cs_begin = uniform(p.grp_ptr[g_begin]);
+      const int cs_end = uniform(p.grp_ptr[g_end]);
+      int gsrc = g_begin;
+      for (int ci = cs_begin - 1; ci < cs_end; ++ci) {
+        int fs = -1, rs = -1;
+        uint32_t srow = 0u;
+        double wi = wa;
+        if (ci >= cs_begin) {
+          while (uniform(p.grp_ptr[gsrc + 1]) <= ci) ++gsrc;
+          fs = uniform(p.grp_fr[gsrc] >> 8);
+          rs = uniform(p.grp_fr[gsrc] & 0xff);
+          srow = uniform(p.child_rowoff[ci]);
+          wi = a.w_src[uniform(p.child_term[ci])];
+        }
+        // sink members: the dominator, then the children of its groups
+        const int cd_begin = q.sgrp_ptr[sg_begin];
+        const int cd_end = q.sgrp_ptr[sg_end];
+        int gsnk = sg_begin;
+        for (int cj = cd_begin - 1; cj < cd_end; ++cj) {
+          int fk = -1, ck = -1;
+          uint32_t scol = 0u;
+          double wj = wb;
+          if (cj >= cd_begin) {
+            while (q.sgrp_ptr[gsnk + 1] <= cj) ++gsnk;
+            fk = q.sgrp_fc[gsnk] >> 8;
+            ck = q.sgrp_fc[gsnk] & 0xff;
+            scol = q.schild_coloff[cj];
+            wj = a.w_snk[q.schild_term[cj]];
+          }
+          double Dre = 1.0, Dim = 0.0;
+          for (int f = 0; f < F; ++f) {
+            const int o = p.off[f];
+            uint32_t co[N];
+#pragma unroll
+            for (int c = 0; c < N; ++c) co[c] = q.sdom_coloff[(size_t)(o + c) * pad + k];
+            double dre, dim;
+            block_det2<N>(lds, rowoff_d + o, f == fs ? rs : -1, srow, co, f == fk ? ck : -1,
+                          scol, dre, dim);
+            const double tr = Dre * dre - Dim * dim;
+            Dim = Dre * dim + Dim * dre;
+            Dre = tr;
+          }
+          if (need) {
+            fre += wi * wj * Dre;
+            fim += wi * wj * Dim;
+          }
+        }
+      }
+      if (need) {
+        vre = fre;
+        vim = fim;
+        ++n_fallback;
+      }
+    }
+    if (valid) {
+      acc_re += vre;
+      acc_im += vim;
+    }
+  }
+
+  __shared__ double red[kWavesPerBlock][2];
+  const double s0 = wave_sum(acc_re), s1 = wave_sum(acc_im);
+  if (lane == 0) {
+    red[wave][0] = s0;
+    red[wave][1] = s1;
+  }
+  if (a.fallback) {
+    uint32_t nf = n_fallback;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) nf += __shfl_xor(nf, o, kWave);
+    if (lane == 0 && nf) atomicAdd(a.fallback, (unsigned long long)nf);
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double v = 0.0;
+    if (threadIdx.x < 2) {
+#pragma unroll
+      for (int w = 0; w < kWavesPerBlock; ++w) v += red[w][threadIdx.x];
+    }
+    a.partial[((size_t)t * a.n_blk_t + chunk) * 3 + threadIdx.x] = v;
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void contract_two_sided_kernel(ContractArgs a) {
+  extern __shared__ double2 smem[];
+  two_sided_tile<N>(a, blockIdx.y, blockIdx.x, smem);
+}
+
+template <int N>
+static hipError_t launch_two_sided_n(const ContractArgs& a, hipStream_t s) {
+  dim3 grid(a.n_blk_t, a.T);
+  const size_t lds = (size_t)a.plan.M * a.plan.M * sizeof(double2);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&contract_two_sided_kernel<N>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((contract_two_sided_kernel<N>), grid, dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_contract_two_sided(const ContractArgs& a, int n, double2* C, hipStream_t s) {
+  hipError_t e;
+  switch (n) {
+#define MHC_CASE(NN)                     \
+  case NN:                               \
+    e = launch_two_sided_n<NN>(a, s);    \
+    break;
+    MHC_CASE(1) MHC_CASE(2) MHC_CASE(3) MHC_CASE(4) MHC_CASE(5) MHC_CASE(6) MHC_CASE(7)
+    MHC_CASE(8)
+#undef MHC_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  return launch_reduce(a, C, nullptr, s);
+}
+
+}  // namespace kern
+}  // namespace mhc

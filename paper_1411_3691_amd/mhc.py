@@ -20,7 +20,7 @@ import torch
 from . import _lib
 from ._lib import check, lib
 
-METHODS = {"plain": _lib.PLAIN_LU, "tree": _lib.UPDATE_TREE}
+METHODS = {"plain": _lib.PLAIN_LU, "tree": _lib.UPDATE_TREE, "tree2": _lib.UPDATE_TREE2}
 POLICIES = {"R1": _lib.GREEDY_R1, "R2": _lib.GREEDY_R2}
 
 
@@ -127,6 +127,12 @@ class Plan:
     @property
     def M(self):
         return self.snk.M
+
+    def attach_sink_tree(self, tree: Tree) -> None:
+        """Enables method "tree2" (source and sink update trees); ``tree``
+        must be built on this plan's sink terms."""
+        check(lib().mhc_plan_attach_sink_tree(self._h, tree.handle, _stream_ptr()))
+        self.snk_tree = tree
 
     def status(self) -> dict:
         """Counters over completed calls (synchronises the device)."""

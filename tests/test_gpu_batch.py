@@ -137,5 +137,25 @@ def test_lane_schedule_refuses_uneven_jobs():
                                                                  with_scale=True)
     for j in range(2):
         assert torch.all(torch.abs(C[j] - R[j]) <= 1e-12 * RA[j])
-    with pytest.raises(ValueError):
-        mhc.Batch(plans, [w.T for w in ws], "tree")(S[:-1] + [S[0]], a, b)
+    with pytest.raises(ValueError):       # a slice missing from the last job's S
+        mhc.Batch(plans, [w.T for w in ws], "tree")(S[:-1] + [S[-1][1:]], a, b)
+
+
+def test_autotune_picks_a_schedule_and_caches_it(tmp_path):
+    from paper_1411_3691_amd import autotune
+    ws = small_jobs()
+    plans, S, a, b = upload(ws)
+    T = [w.T for w in ws]
+    path = str(tmp_path / "tune.json")
+    grid = dict(kernel=["auto", "group"], blocks_per_cu=[1, 2], items_per_tile=[32])
+    sched = autotune.tune(plans, T, "tree", S, a, b, cache=path, grid=grid, reps=2)
+    assert sched in autotune.candidates(plans, grid)
+    assert autotune.load_cache(path)[autotune.shape_key(plans, T, "tree")]["schedule"] == sched
+    # a second call reads the cache (no candidate is run: an empty grid
+    # would have nothing to time)
+    assert autotune.tune(plans, T, "tree", S, a, b, cache=path,
+                         grid=dict(kernel=[], blocks_per_cu=[], items_per_tile=[])) == sched
+    C = mhc.Batch(plans, T, "tree", sched)(S, a, b)
+    R, RA = mhc.Batch(plans, T, "tree")(S, a, b, with_scale=True)
+    for j in range(len(ws)):
+        assert torch.all(torch.abs(C[j] - R[j]) <= 1e-12 * RA[j]), j
