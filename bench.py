@@ -58,6 +58,47 @@ def tree_flops(T, n_snk, nf, tree) -> float:
     return float(T) * n_snk * per_sink
 
 
+def _per_flavour(tree, F):
+    """Per dominator: children and (row, flavour) groups in each flavour."""
+    import numpy as np
+    owner, flav, pos = tree["owner"], tree["flav"], tree["pos"]
+    doms = np.flatnonzero(owner == np.arange(len(owner)))
+    index = {int(d): k for k, d in enumerate(doms)}
+    ch = np.zeros((len(doms), F))
+    gr = np.zeros((len(doms), F))
+    seen = set()
+    for u in np.flatnonzero(owner != np.arange(len(owner))).tolist():
+        k, f = index[int(owner[u])], int(flav[u])
+        ch[k, f] += 1
+        key = (k, f, int(pos[u]))
+        if key not in seen:
+            seen.add(key)
+            gr[k, f] += 1
+    return ch, gr
+
+
+def two_sided_flops(T, nf, src_tree, snk_tree) -> float:
+    """Per slice, over every (source dominator, sink dominator): the
+    dominators' blocks factorised; one column solve per source group and one
+    row solve per sink group; one ratio per child on either side; one row
+    solve z_c per source child in each flavour where the sink dominator has
+    children; per same-block (source child, sink child) pair a dot of n
+    (8n + 6) and per (source child, sink group) the kappa product (10)."""
+    F = len(nf)
+    n = nf[0]
+    cs, gs = _per_flavour(src_tree, F)
+    ck, gk = _per_flavour(snk_tree, F)
+    na, nb = len(cs), len(ck)
+    total = na * nb * float(F * f_lu(n) + 11)
+    total += nb * float((gs * f_solve(n) + cs * f_ratio(n)).sum())
+    total += na * float((gk * f_solve(n) + ck * f_ratio(n)).sum())
+    for f in range(F):
+        total += cs[:, f].sum() * float((ck[:, f] > 0).sum()) * f_solve(n)
+        total += cs[:, f].sum() * ck[:, f].sum() * (8 * n + 6)
+        total += cs[:, f].sum() * gk[:, f].sum() * 10
+    return float(T) * total
+
+
 def plain_flops(T, n_src, n_snk, nf) -> float:
     return float(T) * n_src * n_snk * (sum(f_lu(n) for n in nf) + 11)
 
@@ -255,6 +296,26 @@ def main():
 
     wall_tree, ev_tree, C_tree = timed("tree")
     wall_plain, ev_plain, C_plain = timed("plain")
+    two = None
+    if len(set(w.nf)) == 1 and w.nf[0] <= 8:
+        # the two-sided extension: sink terms in their own update tree
+        t0 = time.perf_counter()
+        stree = mhc.Tree(snk)
+        t_stree = time.perf_counter() - t0
+        plan.attach_sink_tree(stree)
+        wall_two, ev_two, C_two = timed("tree2")
+        ev_two_ms = float(np.mean(ev_two))
+        fl_two = two_sided_flops(w.T, w.nf, tree.export(), stree.export())
+        ach_two = fl_two / (ev_two_ms * 1e-3) / 1e12
+        two = {"value": w.n_pairs / (wall_two / args.steps),
+               "ms_per_step": wall_two * 1e3 / args.steps, "kernel_ms": ev_two_ms,
+               "flops_per_step": fl_two, "tflops": ach_two,
+               "frac": ach_two / FP64_PEAK_TFLOPS,
+               "speedup_vs_plain": wall_plain / wall_two,
+               "speedup_vs_one_sided": wall_tree / wall_two,
+               "max_rel_diff_vs_plain": float(np.max(np.abs(C_two - C_plain)) /
+                                              max(1e-300, float(np.max(np.abs(C_plain))))),
+               "sink_tree": {**stree.stats(), "build_s": t_stree}}
     pairs = w.n_pairs
     ms_tree = wall_tree * 1e3 / args.steps
     ms_plain = wall_plain * 1e3 / args.steps
@@ -296,6 +357,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None},
         "cpu_baseline": cpu,
+        "two_sided": two,
     }
     print(json.dumps(out), flush=True)
 

@@ -128,9 +128,9 @@ void mhc_tree_destroy(mhc_tree* tree);
 /* Device plan: the source tree and the sink terms uploaded once to the
  * current HIP device (Sec. 3: built once and reused across configurations).
  * Both term sets must have the same flavour structure and M.  Flavour blocks
- * may differ in size; the largest must be <= 24, and one slice of S
- * (M * M * 16 bytes) must fit in 150 KiB (M <= 96); otherwise
- * MHC_E_UNSUPPORTED.  Enqueues the uploads on `stream` and waits for them. */
+ * may differ in size; the largest must be <= 24, and one slice of S as the
+ * kernels keep it in LDS (rows padded to M + 1 entries, M * (M + 1) * 16
+ * bytes) must fit in 150 KiB (M <= 97); otherwise MHC_E_UNSUPPORTED.  Enqueues the uploads on `stream` and waits for them. */
 mhc_status mhc_plan_create(const mhc_tree* src_tree, const mhc_terms* snk,
                            void* stream, mhc_plan** out);
 void mhc_plan_destroy(mhc_plan* plan);
@@ -164,7 +164,7 @@ mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
  * definitions); dC/dw from bilinearity.  Inputs as for mhc_contract; gC is
  * complex128 [T].  Any output pointer may be NULL (not written).  At most 4
  * flavour blocks; S_t and its gradient must fit in LDS together
- * (2 * M * M * 16 bytes).  A flavour block with an exactly zero pivot
+ * (2 * M * (M + 1) * 16 bytes).  A flavour block with an exactly zero pivot
  * contributes nothing to gS and is counted (mhc_plan_status).  Device
  * scratch is allocated on the plan at the first call (and grown when T
  * grows). */

@@ -39,13 +39,12 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_kernel(AdjointArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uniform(threadIdx.x / kWave);
   const int MM = p.M * p.M;
-  double2* Sl = smem;            // S_t
-  double2* gl = smem + MM;       // grad S_t accumulator
+  const int LL = p.M * lds_row(p.M);
+  double2* Sl = smem;            // S_t (padded rows)
+  double2* gl = smem + LL;       // grad S_t accumulator, same layout
   const double2* St = a.S + (size_t)t * MM;
-  for (int e = threadIdx.x; e < MM; e += kBlock) {
-    Sl[e] = St[e];
-    gl[e] = make_double2(0.0, 0.0);
-  }
+  stage_slice(St, Sl, p.M, kBlock);
+  for (int e = threadIdx.x; e < LL; e += kBlock) gl[e] = make_double2(0.0, 0.0);
   __syncthreads();
   const char* lds = reinterpret_cast<const char*>(Sl);
   char* glds = reinterpret_cast<char*>(gl);
@@ -172,7 +171,7 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_kernel(AdjointArgs a) {
     a.part_wsnk[(size_t)t * p.n_snk_pad + sb * kWave + threadIdx.x] = v;
   }
   double2* dst = a.part_gS + ((size_t)t * a.n_sblk + sb) * MM;
-  for (int e = threadIdx.x; e < MM; e += kBlock) dst[e] = gl[e];
+  for (int e = threadIdx.x; e < MM; e += kBlock) dst[e] = gl[(e / p.M) * lds_row(p.M) + e % p.M];
 }
 
 // grad S[t][e] = sum over sink blocks of the partials (fixed order)
@@ -212,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void reduce_w(const double* part_src, const
 template <int N>
 static hipError_t launch_adj_n(const AdjointArgs& a, hipStream_t s) {
   dim3 grid(a.n_sblk, a.T);
-  size_t lds = 2 * (size_t)a.plan.M * a.plan.M * sizeof(double2);
+  size_t lds = 2 * lds_slice_bytes(a.plan.M);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adjoint_kernel<N>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

@@ -77,7 +77,7 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
 
   // Stage S_t into LDS (16 B per lane per step, coalesced).
   const double2* St = a.S + (size_t)t * MM;
-  for (int e = threadIdx.x; e < MM; e += kBlock) smem[e] = St[e];
+  stage_slice(St, smem, p.M, kBlock);
   __syncthreads();
   const char* lds = reinterpret_cast<const char*>(smem);
 
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void reduce_partials(const double* partial,
 template <int N, bool TREE, int MODE>
 static hipError_t launch_one(const ContractArgs& a, hipStream_t s) {
   dim3 grid(a.n_blk_t, a.T);
-  size_t lds = (size_t)a.plan.M * a.plan.M * sizeof(double2);
+  size_t lds = lds_slice_bytes(a.plan.M);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&contract_kernel<N, TREE, MODE>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

@@ -31,8 +31,31 @@ __device__ __forceinline__ void cinv(double pr, double pi, double mag,
   vi = __builtin_amdgcn_ldexp(-b * r, -e);
 }
 
+// The LDS copy of S_t keeps rows of M + 1 complex numbers (one unused):
+// with a stride of M * 16 bytes (a multiple of 128 for M = 12 k) the lanes
+// that read one column of different rows would all hit the same banks.
+__host__ __device__ constexpr int lds_row(int M) { return M + 1; }
+__host__ __device__ constexpr size_t lds_slice_bytes(int M) {
+  return (size_t)M * lds_row(M) * 16;
+}
+
+// Copies S_t (M x M, row-major) into the padded LDS layout.
+__device__ __forceinline__ void stage_slice(const double2* St, double2* smem, int M, int nthreads) {
+  const int ld = lds_row(M);
+  const int dr = nthreads / M, dc = nthreads % M;
+  for (int r = threadIdx.x / M, c = threadIdx.x % M; r < M;) {
+    smem[r * ld + c] = St[r * M + c];
+    r += dr;
+    c += dc;
+    if (c >= M) {
+      c -= M;
+      ++r;
+    }
+  }
+}
+
 // G[m][n] = S_t[row_m][col_n]: rowoff/coloff are byte offsets into the LDS
-// copy of S_t (row * M * 16 and col * 16).
+// copy of S_t (row * (M + 1) * 16 and col * 16).
 template <int N>
 __device__ __forceinline__ void gather(const char* lds, const uint32_t (&rowoff)[N],
                                        const uint32_t (&coloff)[N],

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "contract_kernels.h"
+#include "lu_device.h"
 #include "mhc_internal.h"
 
 using mhc::fail;
@@ -83,9 +84,10 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   if (nmax > 24)
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_plan_create: flavour blocks larger than 24 are not supported");
-  if ((size_t)src.M * src.M * 16 > 150 * 1024)
+  if (mhc::kern::lds_slice_bytes(src.M) > 150 * 1024)
     return fail(MHC_E_UNSUPPORTED,
-                "mhc_plan_create: a slice of S (M*M*16 bytes) must fit in 150 KiB of LDS");
+                "mhc_plan_create: a slice of S (M*(M+1)*16 bytes in LDS) must fit in "
+                "150 KiB");
 
   mhc_plan* pl = new (std::nothrow) mhc_plan();
   if (!pl) return fail(MHC_E_OOM, "mhc_plan_create: out of host memory");
@@ -109,7 +111,7 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   pl->snk_idx = snk->idx;
 
   const int sn = src.sn;
-  const uint32_t row_bytes = (uint32_t)src.M * 16u;
+  const uint32_t row_bytes = (uint32_t)mhc::kern::lds_row(src.M) * 16u;  // LDS row stride
   std::vector<int32_t> dom_term(tree->dom_order);
   std::vector<uint32_t> dom_rowoff((size_t)pl->n_dom * sn);
   for (int k = 0; k < pl->n_dom; ++k)
@@ -403,7 +405,7 @@ mhc_status mhc_contract_backward(mhc_plan* pl, int32_t T, const void* S,
   if (!pl->uniform_n || pl->n > 8)
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_contract_backward: flavour blocks must share one size n <= 8");
-  if ((size_t)2 * pl->M * pl->M * 16 > 160 * 1024 - 4096)
+  if (2 * mhc::kern::lds_slice_bytes(pl->M) > 160 * 1024 - 4096)
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_contract_backward: S_t and its gradient must fit in LDS");
   int cur = -1;
@@ -574,7 +576,7 @@ mhc_status batch_build(mhc_batch* b) {
       buckets.push_back(Bucket{narrow, key_n, 0, {}, {}});
       bk = &buckets.back();
     }
-    bk->lds = std::max(bk->lds, (size_t)pl->M * pl->M * 16);
+    bk->lds = std::max(bk->lds, mhc::kern::lds_slice_bytes(pl->M));
     for (int t = 0; t < a.T; ++t) {
       jt.push_back(make_int2(j, t));
       for (int c = 0; c < n_blk_t; ++c) {

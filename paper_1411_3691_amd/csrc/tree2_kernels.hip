@@ -110,7 +110,7 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
   const int wave = uniform(threadIdx.x / kWave);
   const int MM = p.M * p.M;
   const double2* St = a.S + (size_t)t * MM;
-  for (int e = threadIdx.x; e < MM; e += kBlock) smem[e] = St[e];
+  stage_slice(St, smem, p.M, kBlock);
   __syncthreads();
   const char* lds = reinterpret_cast<const char*>(smem);
 
@@ -349,7 +349,7 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void contract_two_sided_kernel(ContractArgs a) {
+__global__ __launch_bounds__(kBlock, 2) void contract_two_sided_kernel(ContractArgs a) {
   extern __shared__ double2 smem[];
   two_sided_tile<N>(a, blockIdx.y, blockIdx.x, smem);
 }
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void contract_two_sided_kernel(ContractArgs
 template <int N>
 static hipError_t launch_two_sided_n(const ContractArgs& a, hipStream_t s) {
   dim3 grid(a.n_blk_t, a.T);
-  const size_t lds = (size_t)a.plan.M * a.plan.M * sizeof(double2);
+  const size_t lds = lds_slice_bytes(a.plan.M);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&contract_two_sided_kernel<N>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

@@ -37,17 +37,38 @@ namespace kern {
 constexpr int kWideBlock = 512;
 constexpr int kWideWaves = kWideBlock / kWave;
 
+// A double moved across lanes by a DPP row rotation (within each row of 16
+// lanes): lane i receives lane (i + R) mod 16 of its row.
+template <int R>
+__device__ __forceinline__ double row_ror(double v) {
+  constexpr int ctrl = 0x120 + R;   // DPP row_ror:R
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum / max over the GROUP lanes of a group: rotations by 8, 4, 2, 1 within
+// each row of 16 (every lane forms the same pairs, so all lanes get the
+// same bits), then one exchange between the two rows of a 32-lane group.
 template <int GROUP>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GROUP);
+  static_assert(GROUP == 16 || GROUP == 32, "groups are one or two DPP rows");
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  v += row_ror<1>(v);
+  if (GROUP == 32) v += __shfl_xor(v, 16, 32);
   return v;
 }
 
 template <int GROUP>
 __device__ __forceinline__ double group_max(double v) {
-#pragma unroll
-  for (int o = GROUP / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, GROUP));
+  static_assert(GROUP == 16 || GROUP == 32, "groups are one or two DPP rows");
+  v = fmax(v, row_ror<8>(v));
+  v = fmax(v, row_ror<4>(v));
+  v = fmax(v, row_ror<2>(v));
+  v = fmax(v, row_ror<1>(v));
+  if (GROUP == 32) v = fmax(v, __shfl_xor(v, 16, 32));
   return v;
 }
 
@@ -223,7 +244,7 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
   const int gsel = lane / GROUP;       // which sink of the wave
   const int MM = p.M * p.M;
   const double2* St = a.S + (size_t)t * MM;
-  for (int e = threadIdx.x; e < MM; e += kWideBlock) smem[e] = St[e];
+  stage_slice(St, smem, p.M, kWideBlock);
   __syncthreads();
   const char* lds = reinterpret_cast<const char*>(smem);
 
@@ -466,7 +487,7 @@ __global__ __launch_bounds__(kWideBlock) void batch_wide_kernel(BatchArgs b) {
 template <int GROUP, int NMAX, bool TREE, int MODE>
 static hipError_t launch_wide_one(const ContractArgs& a, hipStream_t s) {
   dim3 grid(a.n_blk_t, a.T);
-  const size_t lds = (size_t)a.plan.M * a.plan.M * sizeof(double2);
+  const size_t lds = lds_slice_bytes(a.plan.M);
   hipError_t e = hipFuncSetAttribute(
       reinterpret_cast<const void*>(&contract_wide_kernel<GROUP, NMAX, TREE, MODE>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
