@@ -26,6 +26,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
+
+# HBM bytes per launch of the update-tree kernel on the mid workload, from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script
+# (--copy-probe), each scaled by the same counter's reading for a 256 MiB
+# device copy (fetch x 1.9997, write x 1.0).  Valid only for the kernel
+# sources they were measured on (SHA-256 below); null otherwise.
+TRAFFIC = {
+    "workload": "mid",
+    "bytes": 6983.1 * 1.99973 * 1024 + 3680.0 * 1024,
+    "sources": {
+        "paper_1411_3691_amd/csrc/contract_kernels.hip":
+            "d324102ece8ab21ff1226426f439bdbcf391c5db88b99f07e69879bd8cac0301",
+        "paper_1411_3691_amd/csrc/lu_device.h":
+            "0b2dae7d61d15c7903d0337049dca0125cfcfd99ab685ae43a18a1592b846f9b",
+        "paper_1411_3691_amd/csrc/contract_kernels.h":
+            "6365fe718a93463d8269a50c9a3f4e2431c375b915bebca9ea7650efd5f63c84",
+    },
+}
+
+
+def measured_traffic(workload: str):
+    """TRAFFIC["bytes"] if the kernel sources are the ones it was measured
+    on, else None."""
+    import hashlib
+    if workload != TRAFFIC["workload"]:
+        return None
+    for rel, sha in TRAFFIC["sources"].items():
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != sha:
+                    return None
+        except OSError:
+            return None
+    return TRAFFIC["bytes"]
 METRIC = "complex128 det-pairs/sec: update-tree vs plain batched LU, same GPU, 1e-11"
 
 
@@ -245,6 +279,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="one 256 MiB device-to-device copy before timing (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the contraction has no multi-GPU path "
@@ -276,6 +313,13 @@ def main():
     ws = torch.from_numpy(np.ascontiguousarray(w.w_src)).to(dev)
     wk = torch.from_numpy(np.ascontiguousarray(w.w_snk)).to(dev)
     C = torch.empty(w.T, dtype=torch.complex128, device=dev)
+    if args.copy_probe:
+        a_ = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        b_ = torch.empty_like(a_)
+        torch.cuda.synchronize()
+        b_.copy_(a_)          # 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        del a_, b_
     torch.cuda.synchronize()
 
     def timed(method):
@@ -296,6 +340,24 @@ def main():
 
     wall_tree, ev_tree, C_tree = timed("tree")
     wall_plain, ev_plain, C_plain = timed("plain")
+    back = None
+    if args.workload == "grad":
+        # the adjoint (mhc_contract_backward): grad S and both weight
+        # gradients for a random upstream gradient
+        gC = torch.from_numpy(np.random.default_rng(0).standard_normal(w.T)
+                              + 1j * np.random.default_rng(1).standard_normal(w.T)).to(dev)
+        for _ in range(args.warmup):
+            mhc.contract_backward(plan, S, ws, wk, gC)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            mhc.contract_backward(plan, S, ws, wk, gC)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / args.steps
+        back = {"ms_per_step": ms_b, "det_pairs_per_s": w.n_pairs / (ms_b * 1e-3)}
     two = None
     if len(set(w.nf)) == 1 and w.nf[0] <= 8:
         # the two-sided extension: sink terms in their own update tree
@@ -355,9 +417,11 @@ def main():
         "tree": {**st, "rho": st["n_dom"] / st["n_terms"], "build_s": t_tree,
                  "kernel_ms": ev_tree_ms, "flops_per_step": fl_tree},
         "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None},
+                     "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(args.workload)},
         "cpu_baseline": cpu,
         "two_sided": two,
+        "backward": back,
     }
     print(json.dumps(out), flush=True)
 
