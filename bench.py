@@ -114,10 +114,11 @@ def _per_flavour(tree, F):
 def two_sided_flops(T, nf, src_tree, snk_tree) -> float:
     """Per slice, over every (source dominator, sink dominator): the
     dominators' blocks factorised; one column solve per source group and one
-    row solve per sink group; one ratio per child on either side; one row
-    solve z_c per source child in each flavour where the sink dominator has
+    row solve per sink group; one ratio per child on either side; one column
+    solve q_d per sink child in each flavour where the source dominator has
     children; per same-block (source child, sink child) pair a dot of n
-    (8n + 6) and per (source child, sink group) the kappa product (10)."""
+    plus the corner and the weight (8n + 6) and per (source group, sink
+    child) the kappa product (10)."""
     F = len(nf)
     n = nf[0]
     cs, gs = _per_flavour(src_tree, F)
@@ -127,9 +128,9 @@ def two_sided_flops(T, nf, src_tree, snk_tree) -> float:
     total += nb * float((gs * f_solve(n) + cs * f_ratio(n)).sum())
     total += na * float((gk * f_solve(n) + ck * f_ratio(n)).sum())
     for f in range(F):
-        total += cs[:, f].sum() * float((ck[:, f] > 0).sum()) * f_solve(n)
+        total += ck[:, f].sum() * float((cs[:, f] > 0).sum()) * f_solve(n)
         total += cs[:, f].sum() * ck[:, f].sum() * (8 * n + 6)
-        total += cs[:, f].sum() * gk[:, f].sum() * 10
+        total += gs[:, f].sum() * ck[:, f].sum() * 10
     return float(T) * total
 
 
@@ -340,6 +341,27 @@ def main():
 
     wall_tree, ev_tree, C_tree = timed("tree")
     wall_plain, ev_plain, C_plain = timed("plain")
+    abl = None
+    if args.workload == "mid":
+        # the paper's variants (Sec. 4, Fig. 1 caption) on the same inputs:
+        # LU without pivoting, and updates without shared solves
+        abl = {}
+        for name, method in (("plain_unpivoted", "plain_unpivoted"),
+                             ("tree_unpivoted", "tree_unpivoted")):
+            wall_a, ev_a, _ = timed(method)
+            abl[name] = {"ms_per_step": wall_a * 1e3 / args.steps,
+                         "kernel_ms": float(np.mean(ev_a)),
+                         "value": w.n_pairs / (wall_a / args.steps)}
+        tree_ns = mhc.Tree(src, share=False)
+        plan_ns = mhc.Plan(tree_ns, snk)
+        plan_main = plan
+        plan = plan_ns
+        wall_a, ev_a, _ = timed("tree")
+        plan = plan_main
+        abl["tree_without_sharing"] = {"ms_per_step": wall_a * 1e3 / args.steps,
+                                       "kernel_ms": float(np.mean(ev_a)),
+                                       "value": w.n_pairs / (wall_a / args.steps),
+                                       "n_groups": tree_ns.stats()["n_groups"]}
     back = None
     if args.workload == "grad":
         # the adjoint (mhc_contract_backward): grad S and both weight
@@ -421,6 +443,7 @@ def main():
                      "traffic": measured_traffic(args.workload)},
         "cpu_baseline": cpu,
         "two_sided": two,
+        "ablations": abl,
         "backward": back,
     }
     print(json.dumps(out), flush=True)

@@ -60,15 +60,24 @@ typedef enum {
  *   graph of remaining terms (lowest index on ties), then remove it and its
  *   remaining neighbours. */
 enum { MHC_GREEDY_R1 = 1, MHC_GREEDY_R2 = 2 };
+/* Flag or-ed into the policy of mhc_tree_build: every child gets its own
+ * group, so siblings that change the same row do not share the solve
+ * (Sec. 2 "updating" without the "caching" of Fig. 1; an ablation). */
+enum { MHC_TREE_NO_SHARING = 0x100 };
 
 /* Contraction methods. */
 enum {
   MHC_PLAIN_LU = 0,    /* pivoted LU of every pair and flavour block (Sec. 2) */
   MHC_UPDATE_TREE = 1, /* dominator LU + rank-1 updates (Secs. 2-3)          */
-  MHC_UPDATE_TREE2 = 2 /* source and sink trees: one LU per (source dominator,
-                        * sink dominator), rank-1 row and column updates and
-                        * the rank-2 form for pairs changed on both sides;
-                        * needs mhc_plan_attach_sink_tree                    */
+  MHC_UPDATE_TREE2 = 2, /* source and sink trees: one LU per (source dominator,
+                         * sink dominator), rank-1 row and column updates and
+                         * the rank-2 form for pairs changed on both sides;
+                         * needs mhc_plan_attach_sink_tree                    */
+  /* Ablations (Sec. 4 compares LAPACK's pivoted LU with a custom LU without
+   * pivoting): the same two methods with the diagonal as every pivot.  Not
+   * backward stable; every block must have one size n <= 8. */
+  MHC_PLAIN_LU_UNPIVOTED = 3,
+  MHC_UPDATE_TREE_UNPIVOTED = 4
 };
 
 typedef struct mhc_terms mhc_terms;
@@ -105,8 +114,9 @@ mhc_status mhc_terms_shape(const mhc_terms* terms, int32_t* n_terms,
 /* Update tree over source terms (Sec. 3).  Two terms are neighbours when
  * their index tuples differ in exactly one position; that position is the
  * flavour block f and the row r that changes (Sec. 2: G^(jk) = G^(ik) +
- * e_r v^T).  The greedy rule `policy` picks dominators; every other term
- * becomes a child of the first dominator whose neighbourhood covered it.
+ * e_r v^T).  The greedy rule `policy` (MHC_GREEDY_R1 or R2, optionally
+ * | MHC_TREE_NO_SHARING) picks dominators; every other term becomes a child
+ * of the first dominator whose neighbourhood covered it.
  * Host only; depends on neither S nor the weights, so one tree serves every
  * gauge configuration and time slice. */
 mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,

@@ -25,6 +25,9 @@ GREEDY_R2 = 2
 PLAIN_LU = 0
 UPDATE_TREE = 1
 UPDATE_TREE2 = 2
+PLAIN_LU_UNPIVOTED = 3
+UPDATE_TREE_UNPIVOTED = 4
+TREE_NO_SHARING = 0x100
 SCHED_AUTO = 0
 SCHED_LANE = 1
 SCHED_GROUP = 2

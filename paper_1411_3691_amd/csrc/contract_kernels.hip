@@ -60,7 +60,8 @@ __device__ __forceinline__ void child_det_direct(const char* lds,
   lu<N, false>(gr, gi, dre, dim, perm, z);
 }
 
-// MODE bit 0: accumulate A(t) = sum |w w d|; bit 1: write every pair det.
+// MODE bit 0: accumulate A(t) = sum |w w d|; bit 1: write every pair det;
+// bit 2: no pivoting (ablation).
 // One tile: slice t, the chunk-th strided share of the slice's work items.
 // The workgroup stages S_t in LDS (smem), walks its items and writes one
 // partial (re, im, A) for (t, chunk).
@@ -68,6 +69,7 @@ template <int N, bool TREE, int MODE>
 __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chunk,
                                           double2* smem) {
   constexpr bool WITH_A = (MODE & 1) != 0;
+  constexpr bool PIVOT = (MODE & 4) == 0;
   constexpr bool WITH_PAIRS = (MODE & 2) != 0;
   const PlanView& p = a.plan;
   __syncthreads();  // the previous tile of this workgroup is done with LDS
@@ -131,7 +133,7 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
           int perm[N];
           bool z;
           gather<N>(lds, ro, co, gr, gi);
-          lu<N, TREE>(gr, gi, Dpre_re[f], Dpre_im[f], perm, z);
+          lu<N, TREE, PIVOT>(gr, gi, Dpre_re[f], Dpre_im[f], perm, z);
         }
       }
     }
@@ -159,7 +161,7 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
       // The tree keeps the multipliers for every dominator block: nearly
       // every dominator has groups in every flavour, and a single
       // factorisation path keeps the register allocation within budget.
-      lu<N, TREE>(gr, gi, dre, dim, perm, zero);
+      lu<N, TREE, PIVOT>(gr, gi, dre, dim, perm, zero);
       if (TREE) {
         double sre = 0.0, sim = 0.0;
         for (int gg = g; gg < g_f_end; ++gg) {
@@ -369,23 +371,28 @@ static hipError_t launch_one(const ContractArgs& a, hipStream_t s) {
 }
 
 template <int N>
-static hipError_t launch_n(const ContractArgs& a, bool tree, bool diag, hipStream_t s) {
+static hipError_t launch_n(const ContractArgs& a, bool tree, bool diag, bool pivot,
+                           hipStream_t s) {
+  if (!pivot) {
+    if (tree) return diag ? launch_one<N, true, 7>(a, s) : launch_one<N, true, 4>(a, s);
+    return diag ? launch_one<N, false, 7>(a, s) : launch_one<N, false, 4>(a, s);
+  }
   if (tree) return diag ? launch_one<N, true, 3>(a, s) : launch_one<N, true, 0>(a, s);
   return diag ? launch_one<N, false, 3>(a, s) : launch_one<N, false, 0>(a, s);
 }
 
-hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag,
+hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag, bool pivot,
                            double2* C, double* A, hipStream_t s) {
   hipError_t e;
   switch (n) {
-    case 1: e = launch_n<1>(a, tree, diag, s); break;
-    case 2: e = launch_n<2>(a, tree, diag, s); break;
-    case 3: e = launch_n<3>(a, tree, diag, s); break;
-    case 4: e = launch_n<4>(a, tree, diag, s); break;
-    case 5: e = launch_n<5>(a, tree, diag, s); break;
-    case 6: e = launch_n<6>(a, tree, diag, s); break;
-    case 7: e = launch_n<7>(a, tree, diag, s); break;
-    case 8: e = launch_n<8>(a, tree, diag, s); break;
+    case 1: e = launch_n<1>(a, tree, diag, pivot, s); break;
+    case 2: e = launch_n<2>(a, tree, diag, pivot, s); break;
+    case 3: e = launch_n<3>(a, tree, diag, pivot, s); break;
+    case 4: e = launch_n<4>(a, tree, diag, pivot, s); break;
+    case 5: e = launch_n<5>(a, tree, diag, pivot, s); break;
+    case 6: e = launch_n<6>(a, tree, diag, pivot, s); break;
+    case 7: e = launch_n<7>(a, tree, diag, pivot, s); break;
+    case 8: e = launch_n<8>(a, tree, diag, pivot, s); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;

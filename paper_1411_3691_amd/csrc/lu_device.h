@@ -148,7 +148,9 @@ __device__ __forceinline__ double pivot_key(double re, double im, int m) {
 // determinant, and keep the permutation (perm[m] = original row now in
 // position m).  Returns det = sgn(P) prod U_kk and whether some pivot was
 // exactly zero.
-template <int N, bool KEEP>
+// PIVOT = false (an ablation of the paper's unpivoted 6x6 LU, Sec. 4):
+// the pivot of step k is the diagonal entry, no rows are exchanged.
+template <int N, bool KEEP, bool PIVOT = true>
 __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
                                    double& dre, double& dim, int (&perm)[N],
                                    bool& zero_pivot) {
@@ -162,6 +164,7 @@ __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) {
+    if (PIVOT) {
     double key = pivot_key(gr[k][k], gi[k][k], k);
 #pragma unroll
     for (int m = k + 1; m < N; ++m) key = fmax(key, pivot_key(gr[m][k], gi[m][k], m));
@@ -218,6 +221,7 @@ __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
       }
     }
     neg = neg != (p != k);
+    }
     const double pr = gr[k][k], pi = gi[k][k];
     const double mag = fabs(pr) + fabs(pi);
     zero_pivot = zero_pivot || (mag == 0.0);

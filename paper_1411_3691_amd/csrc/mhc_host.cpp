@@ -245,6 +245,8 @@ mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
   if (!out) return fail(MHC_E_ARG, "mhc_tree_build: out is NULL");
   *out = nullptr;
   if (!src) return fail(MHC_E_ARG, "mhc_tree_build: NULL terms");
+  const bool share = (policy & MHC_TREE_NO_SHARING) == 0;
+  policy &= ~MHC_TREE_NO_SHARING;
   if (policy != MHC_GREEDY_R1 && policy != MHC_GREEDY_R2)
     return fail(MHC_E_ARG, "mhc_tree_build: policy must be R1 or R2");
   mhc_tree* tr = new (std::nothrow) mhc_tree();
@@ -302,8 +304,8 @@ mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
         return tr->pos[x] < tr->pos[y];
       });
       for (auto it = b; it != e;) {
-        auto jt = it;
-        while (jt != e && tr->flav[*jt] == tr->flav[*it] &&
+        auto jt = it + 1;
+        while (share && jt != e && tr->flav[*jt] == tr->flav[*it] &&
                tr->pos[*jt] == tr->pos[*it])
           ++jt;
         tr->grp_f.push_back(tr->flav[*it]);

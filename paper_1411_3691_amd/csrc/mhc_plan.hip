@@ -314,8 +314,13 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
     return fail(MHC_E_ARG, "mhc_contract: NULL buffer");
   if (T < 1) return fail(MHC_E_ARG, "mhc_contract: T < 1");
   if (T > 65535) return fail(MHC_E_ARG, "mhc_contract: T > 65535");
-  if (method != MHC_PLAIN_LU && method != MHC_UPDATE_TREE && method != MHC_UPDATE_TREE2)
+  if (method != MHC_PLAIN_LU && method != MHC_UPDATE_TREE && method != MHC_UPDATE_TREE2 &&
+      method != MHC_PLAIN_LU_UNPIVOTED && method != MHC_UPDATE_TREE_UNPIVOTED)
     return fail(MHC_E_ARG, "mhc_contract: unknown method");
+  const bool pivot = method != MHC_PLAIN_LU_UNPIVOTED && method != MHC_UPDATE_TREE_UNPIVOTED;
+  if (!pivot && !(pl->uniform_n && pl->n <= 8))
+    return fail(MHC_E_UNSUPPORTED,
+                "mhc_contract: the unpivoted methods need every flavour block of size n <= 8");
   if (method == MHC_UPDATE_TREE2) {
     if (!pl->dev_tree2)
       return fail(MHC_E_STATE, "mhc_contract: no sink tree attached to the plan");
@@ -333,7 +338,7 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_contract: pair_det output supports at most 4 flavour blocks");
   const bool two = method == MHC_UPDATE_TREE2;
-  const bool tree = method == MHC_UPDATE_TREE;
+  const bool tree = method == MHC_UPDATE_TREE || method == MHC_UPDATE_TREE_UNPIVOTED;
   const bool diag = A != nullptr || pair_det != nullptr;
   // one matrix per lane when every block has the same size n <= 8, else one
   // group of lanes per matrix
@@ -381,7 +386,7 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
     e = mhc::kern::launch_contract_two_sided(a, pl->n, static_cast<double2*>(C),
                                              reinterpret_cast<hipStream_t>(stream));
   else if (narrow)
-    e = mhc::kern::launch_contract(a, pl->n, tree, diag, static_cast<double2*>(C), A,
+    e = mhc::kern::launch_contract(a, pl->n, tree, diag, pivot, static_cast<double2*>(C), A,
                                    reinterpret_cast<hipStream_t>(stream));
   else
     e = mhc::kern::launch_contract_wide(a, pl->n, tree, diag, static_cast<double2*>(C), A,

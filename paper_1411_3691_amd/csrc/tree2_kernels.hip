@@ -20,8 +20,11 @@
 // source tree, as in the one-sided kernel) and 64 sink dominators, one per
 // lane, each with its own sink groups and children (per-lane loops; the
 // sink dominators are sorted so that neighbouring lanes have similar
-// counts).  Source children's row vectors z_c = s_c^T G^-1 are solved only
-// in flavours where some lane of the wave has sink children.
+// counts).  Per flavour: the source groups and children first (x_r, rho_c);
+// then each lane walks its sink groups (y_c) and children (sigma_d) once,
+// and where the source dominator has children in the block, solves
+// q_d = G^-1 v_d and runs the wave-uniform source loops for the pair terms
+// beta - alpha = s_c . q_d - alpha.
 //
 // A lane whose dominator block has an exactly zero pivot evaluates every
 // pair of its two partitions by direct LU instead (counted in the plan's
@@ -67,18 +70,29 @@ __device__ __forceinline__ void solve_row(const double (&gr)[N][N], const double
   }
 }
 
-// sum_m b[m] S_t[prow[m]][col]: a row solution against a sink column.
+// x = G^-1 v in place from the factors of lu<N, true>, with (vr, vi) = P v
+// on entry (v permuted to pivot order): L y = P v, then U x = y.
 template <int N>
-__device__ __forceinline__ void dot_col(const char* lds, const uint32_t (&prow)[N], uint32_t col,
-                                        const double (&br)[N], const double (&bi)[N],
-                                        double& re, double& im) {
-  re = 0.0;
-  im = 0.0;
+__device__ __forceinline__ void solve_col(const double (&gr)[N][N], const double (&gi)[N][N],
+                                          double (&vr)[N], double (&vi)[N]) {
 #pragma unroll
-  for (int m = 0; m < N; ++m) {
-    const double2 v = *reinterpret_cast<const double2*>(lds + prow[m] + col);
-    re += br[m] * v.x - bi[m] * v.y;
-    im += br[m] * v.y + bi[m] * v.x;
+  for (int m = 1; m < N; ++m) {
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      vr[m] = vr[m] - gr[m][j] * vr[j] + gi[m][j] * vi[j];
+      vi[m] = vi[m] - gr[m][j] * vi[j] - gi[m][j] * vr[j];
+    }
+  }
+#pragma unroll
+  for (int m = N - 1; m >= 0; --m) {
+    double tr = vr[m], ti = vi[m];
+#pragma unroll
+    for (int j = m + 1; j < N; ++j) {
+      tr = tr - gr[m][j] * vr[j] + gi[m][j] * vi[j];
+      ti = ti - gr[m][j] * vi[j] - gi[m][j] * vr[j];
+    }
+    vr[m] = tr * gr[m][m] - ti * gi[m][m];
+    vi[m] = tr * gi[m][m] + ti * gr[m][m];
   }
 }
 
@@ -171,7 +185,33 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
           if (perm[m] == j) v = ro[j];
         prow[m] = v;
       }
-      // this lane's sink groups in flavour f
+      // the source groups of flavour f (wave-uniform): x_r, rho_c
+      int g_f_end = g;
+      while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
+      for (int gg = g; gg < g_f_end; ++gg) {
+        const int r = uniform(p.grp_fr[gg] & 0xff);
+        double xr[N], xi[N];
+        solve_unit<N>(gr, gi, perm, r, xr, xi);
+        const int c_begin = uniform(p.grp_ptr[gg]);
+        const int c_end = uniform(p.grp_ptr[gg + 1]);
+        for (int c = c_begin; c < c_end; ++c) {
+          const uint32_t crow = uniform(p.child_rowoff[c]);
+          const double wc = a.w_src[uniform(p.child_term[c])];
+          double rr = 0.0, ri = 0.0;
+#pragma unroll
+          for (int n = 0; n < N; ++n) {
+            const double2 sv = *reinterpret_cast<const double2*>(lds + crow + co[n]);
+            rr += sv.x * xr[n] - sv.y * xi[n];
+            ri += sv.x * xi[n] + sv.y * xr[n];
+          }
+          Rre += wc * rr;
+          Rim += wc * ri;
+        }
+      }
+      // this lane's sink groups in flavour f: y_c, sigma_d, and where the
+      // source dominator has children in this block, q_d = G^-1 v_d and the
+      // same-block pair terms (source loops inside are wave-uniform)
+      const bool src_kids = g_f_end > g;
       int sg_f = sg;
       while (sg_f < sg_end && (q.sgrp_fc[sg_f] >> 8) == f) ++sg_f;
       for (int h = sg; h < sg_f; ++h) {
@@ -182,66 +222,59 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
           br[j] = (j == cc) ? 1.0 : 0.0;
           bi[j] = 0.0;
         }
-        solve_row<N>(gr, gi, br, bi);
+        solve_row<N>(gr, gi, br, bi);     // y_c = e_c^T G^-1, as b^T P
         for (int ch = q.sgrp_ptr[h]; ch < q.sgrp_ptr[h + 1]; ++ch) {
+          const uint32_t col = q.schild_coloff[ch];
           const double wd = a.w_snk[q.schild_term[ch]];
-          double sr, si;
-          dot_col<N>(lds, prow, q.schild_coloff[ch], br, bi, sr, si);
+          // P v_d: the new column at the rows in pivot order
+          double vr[N], vi[N];
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const double2 v = *reinterpret_cast<const double2*>(lds + prow[m] + col);
+            vr[m] = v.x;
+            vi[m] = v.y;
+            sr += br[m] * v.x - bi[m] * v.y;
+            si += br[m] * v.y + bi[m] * v.x;
+          }
           Sre += wd * sr;
           Sim += wd * si;
-        }
-      }
-      // the source groups of flavour f (wave-uniform)
-      int g_f_end = g;
-      while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
-      const bool pairs = __builtin_amdgcn_ballot_w64(sg < sg_f) != 0;
-      for (int gg = g; gg < g_f_end; ++gg) {
-        const int r = uniform(p.grp_fr[gg] & 0xff);
-        double xr[N], xi[N];
-        solve_unit<N>(gr, gi, perm, r, xr, xi);
-        const int c_begin = uniform(p.grp_ptr[gg]);
-        const int c_end = uniform(p.grp_ptr[gg + 1]);
-        for (int c = c_begin; c < c_end; ++c) {
-          const uint32_t crow = uniform(p.child_rowoff[c]);
-          const double wc = a.w_src[uniform(p.child_term[c])];
-          double br[N], bi[N];
-          double rr = 0.0, ri = 0.0;
+          if (!src_kids) continue;
+          solve_col<N>(gr, gi, vr, vi);   // q_d = G^-1 v_d
+          double tre = 0.0, tim = 0.0;
+          for (int gg = g; gg < g_f_end; ++gg) {
+            const int r = uniform(p.grp_fr[gg] & 0xff);
+            // kappa = (G^-1)[cc][r] = y_c[r] = b[m] with perm[m] == r
+            double kr = 0.0, ki = 0.0;
 #pragma unroll
-          for (int n = 0; n < N; ++n) {
-            const double2 s = *reinterpret_cast<const double2*>(lds + crow + co[n]);
-            br[n] = s.x;
-            bi[n] = s.y;
-            rr += s.x * xr[n] - s.y * xi[n];
-            ri += s.x * xi[n] + s.y * xr[n];
-          }
-          Rre += wc * rr;
-          Rim += wc * ri;
-          if (pairs) {
-            solve_row<N>(gr, gi, br, bi);   // z_c = s_c^T G^-1, as b^T P
-            for (int h = sg; h < sg_f; ++h) {
-              const int cc = q.sgrp_fc[h] & 0xff;
-              // kappa = (G^-1)[cc][r] = x_r[cc]
-              double kr = xr[0], ki = xi[0];
-#pragma unroll
-              for (int j = 1; j < N; ++j)
-                if (cc == j) {
-                  kr = xr[j];
-                  ki = xi[j];
-                }
-              double tre = 0.0, tim = 0.0;
-              for (int ch = q.sgrp_ptr[h]; ch < q.sgrp_ptr[h + 1]; ++ch) {
-                const uint32_t col = q.schild_coloff[ch];
-                const double wd = a.w_snk[q.schild_term[ch]];
-                double bre, bim;
-                dot_col<N>(lds, prow, col, br, bi, bre, bim);
-                const double2 al = *reinterpret_cast<const double2*>(lds + crow + col);
-                tre += wd * (bre - al.x);
-                tim += wd * (bim - al.y);
+            for (int m = 0; m < N; ++m)
+              if (perm[m] == r) {
+                kr = br[m];
+                ki = bi[m];
               }
-              Kre += wc * (kr * tre - ki * tim);
-              Kim += wc * (kr * tim + ki * tre);
+            double ure = 0.0, uim = 0.0;
+            const int c_begin = uniform(p.grp_ptr[gg]);
+            const int c_end = uniform(p.grp_ptr[gg + 1]);
+            for (int c = c_begin; c < c_end; ++c) {
+              const uint32_t crow = uniform(p.child_rowoff[c]);
+              const double wc = a.w_src[uniform(p.child_term[c])];
+              // beta - alpha = s_c . q_d - S[new row][new column]
+              const double2 al = *reinterpret_cast<const double2*>(lds + crow + col);
+              double bre = -al.x, bim = -al.y;
+#pragma unroll
+              for (int n = 0; n < N; ++n) {
+                const double2 sv = *reinterpret_cast<const double2*>(lds + crow + co[n]);
+                bre += sv.x * vr[n] - sv.y * vi[n];
+                bim += sv.x * vi[n] + sv.y * vr[n];
+              }
+              ure += wc * bre;
+              uim += wc * bim;
             }
+            tre += kr * ure - ki * uim;
+            tim += kr * uim + ki * ure;
           }
+          Kre += wd * tre;
+          Kim += wd * tim;
         }
       }
       g = g_f_end;

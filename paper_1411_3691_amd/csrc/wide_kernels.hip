@@ -83,10 +83,6 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
   }
 }
 
-// Whether the elimination searches the next pivot before finishing the
-// current step's update.
-constexpr bool kLookahead = true;
-
 // Result of eliminating one flavour block.
 struct GJResult {
   double dre, dim;   // det G (same value in every lane of the group)
@@ -101,20 +97,13 @@ struct PivotLanes {
 };
 
 // Gauss-Jordan on the group's matrix.  (ar, ai)[c]: this lane's row
-// (columns c < n; entries at c >= n are zero).  Step k eliminates column k
-// from every row but the pivot row; a row's multiplier l_{m,k} is kept in
-// its column k (which the elimination has just zeroed), so the row
-// operations can be replayed on any right-hand side afterwards
-// (replay_units).  On return, lane m < n holds the reciprocal of its pivot
-// in (ur, ui) and the column it pivoted in (col); piv holds the pivot lane
-// of every step.
-//
-// The pivot of step k + 1 is searched inside step k, right after column
-// k + 1 has been updated and before the other columns are: the search (a
-// reduction across the group and a broadcast) then overlaps with the rest
-// of the update instead of following it.  Columns >= n are updated too
-// (they stay zero), so that each step is one branch-free block.
-template <int GROUP, int NMAX, bool LOOKAHEAD = kLookahead>
+// (columns c < n).  Step k eliminates column k from every row but the
+// pivot row; a row's multiplier l_{m,k} is kept in its column k (which
+// the elimination has just zeroed), so the row operations can be replayed
+// on any right-hand side afterwards (replay_unit).  On return, lane m < n
+// holds the reciprocal of its pivot in (ur, ui) and the column it pivoted
+// in (col); piv holds the pivot lane of every step.
+template <int GROUP, int NMAX>
 __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai)[NMAX], int n,
                                                  int m, double& ur, double& ui, int& col,
                                                  PivotLanes<NMAX>& piv) {
@@ -127,34 +116,27 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
   ui = 0.0;
   col = -1;
   static_for<0, (NMAX + 5) / 6>([&](auto ic) { piv.w[decltype(ic)::value] = 0u; });
-  // pivot of one column among the rows not used yet: largest |Re|+|Im|,
-  // lowest row on ties (the row rank sits in the 5 low mantissa bits); some
-  // row of the group is always unused while k < n, so the max carries a
-  // rank 0 <= p < GROUP (the mask only keeps the lane in range)
-  int np = 0;
-  double npr = 0.0, npi = 0.0;
-  auto search = [&](double cr, double ci) {
-    const double mag = fabs(cr) + fabs(ci);
-    const uint32_t lo = (__double2loint(mag) & ~31u) | (uint32_t)(31 - m);
-    double key = done ? -1.0 : __hiloint2double(__double2hiint(mag), (int)lo);
-    key = group_max<GROUP>(key);
-    np = (31 - (int)(__double2loint(key) & 31u)) & (GROUP - 1);
-    npr = __shfl(cr, gbase + np, 64);
-    npi = __shfl(ci, gbase + np, 64);
-  };
-  search(ar[0], ai[0]);
   static_for<0, NMAX>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     if (k >= n) return;
-    const int p = np;
-    const double pr = npr, pi = npi;
+    // pivot: largest |Re|+|Im| of column k among rows not used yet
+    const double mag = fabs(ar[k]) + fabs(ai[k]);
+    const uint32_t lo = (__double2loint(mag) & ~31u) | (uint32_t)(31 - m);
+    double key = done ? -1.0 : __hiloint2double(__double2hiint(mag), (int)lo);
+    key = group_max<GROUP>(key);
+    // (some row of the group is always unused at step k < n, so the max
+    // carries a rank 0 <= p < GROUP; the mask only keeps the lane in range)
+    const int p = (31 - (int)(__double2loint(key) & 31u)) & (GROUP - 1);
     piv.w[k / 6] |= (uint32_t)p << (5 * (k % 6));
     // sign: rows below p that are still unused each contribute one
     // transposition to the pivot permutation
     const uint64_t open = __builtin_amdgcn_ballot_w64(!done);
     const uint32_t below = (uint32_t)((open >> gbase) & ((1ull << p) - 1ull));
     neg = neg != ((__builtin_popcount(below) & 1) != 0);
+    // pivot row, broadcast to the group
     const int src = gbase + p;
+    const double pr = __shfl(ar[k], src, 64);
+    const double pi = __shfl(ai[k], src, 64);
     const double pmag = fabs(pr) + fabs(pi);
     res.zero = res.zero || (pmag == 0.0);
     const double t = res.dre * pr - res.dim * pi;
@@ -176,23 +158,14 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
       lr = 0.0;
       li = 0.0;
     }
-    auto update = [&](auto cc) {
+    static_for<k + 1, NMAX>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
+      if (c >= n) return;
       const double br = __shfl(ar[c], src, 64);
       const double bi = __shfl(ai[c], src, 64);
       ar[c] = ar[c] - lr * br + li * bi;
       ai[c] = ai[c] - lr * bi - li * br;
-    };
-    if constexpr (LOOKAHEAD) {
-      if constexpr (k + 1 < NMAX) {
-        update(std::integral_constant<int, k + 1>{});
-        search(ar[k + 1], ai[k + 1]);
-      }
-      static_for<k + 2, NMAX>(update);
-    } else {
-      static_for<k + 1, NMAX>(update);
-      if constexpr (k + 1 < NMAX) search(ar[k + 1], ai[k + 1]);
-    }
+    });
     if (!me) {
       ar[k] = lr;
       ai[k] = li;
@@ -205,44 +178,29 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
   return res;
 }
 
-// x_q = G^-1 e_{r_q} for Q unit columns at once (r_q < 0: unused, gives 0)
-// from an elimination: replays its row operations on the unit columns
-// (lane m holds entry m of each); then x[col_m] = E'_m / u_m, returned in
-// (xr, xi)[q] by lane m.  The pivot lane of a step keeps its own column k
-// entry (its pivot), which the step does not use.  The Q chains of
-// broadcasts are independent, so their latencies overlap.
-template <int GROUP, int NMAX, int Q>
-__device__ __forceinline__ void replay_units(const double (&ar)[NMAX], const double (&ai)[NMAX],
-                                             const PivotLanes<NMAX>& piv, const int (&r)[Q],
-                                             int n, int m, double ur, double ui,
-                                             double (&xr)[Q], double (&xi)[Q]) {
+// x = G^-1 e_r from an elimination: replays its row operations on the unit
+// column e_r (lane m holds entry m); then x[col_m] = E'_m / u_m, returned
+// in (xr, xi) by lane m.  The pivot lane of a step keeps its own column k
+// entry (its pivot), which the step does not use.
+template <int GROUP, int NMAX>
+__device__ __forceinline__ void replay_unit(const double (&ar)[NMAX], const double (&ai)[NMAX],
+                                            const PivotLanes<NMAX>& piv, int r, int n, int m,
+                                            double ur, double ui, double& xr, double& xi) {
   const int gbase = (__lane_id() / GROUP) * GROUP;
-  double er[Q], ei[Q];
-  static_for<0, Q>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    er[q] = (m == r[q]) ? 1.0 : 0.0;
-    ei[q] = 0.0;
-  });
+  double er = (m == r) ? 1.0 : 0.0, ei = 0.0;
   static_for<0, NMAX>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     if (k >= n) return;
     const int p = piv.get(k);
-    const bool upd = m != p && m < n;
-    static_for<0, Q>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      const double br = __shfl(er[q], gbase + p, 64);
-      const double bi = __shfl(ei[q], gbase + p, 64);
-      const double nr = er[q] - ar[k] * br + ai[k] * bi;
-      const double ni = ei[q] - ar[k] * bi - ai[k] * br;
-      er[q] = upd ? nr : er[q];
-      ei[q] = upd ? ni : ei[q];
-    });
+    const double br = __shfl(er, gbase + p, 64);
+    const double bi = __shfl(ei, gbase + p, 64);
+    if (m != p && m < n) {
+      er = er - ar[k] * br + ai[k] * bi;
+      ei = ei - ar[k] * bi - ai[k] * br;
+    }
   });
-  static_for<0, Q>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    xr[q] = er[q] * ur - ei[q] * ui;
-    xi[q] = er[q] * ui + ei[q] * ur;
-  });
+  xr = er * ur - ei * ui;
+  xi = er * ui + ei * ur;
 }
 
 // det of the block whose row `rrep` is replaced by the LDS row `newrow`
@@ -375,62 +333,41 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
       double accre = 0.0, accim = 0.0;
       if (TREE && R > 0) {
         double sre = 0.0, sim = 0.0;
-        // per-lane weighted sums when no per-child value is needed: one
-        // group reduction per flavour instead of two per child
-        double lre = 0.0, lim = 0.0;
-        for (int q0 = 0; q0 < R; q0 += 4) {
-          // x = G^-1 e_r for up to four groups at once; lane m holds x[col]
-          int rq[4];
-          static_for<0, 4>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            rq[j] = (q0 + j < R) ? uniform(p.grp_fr[g + q0 + j] & 0xff) : -1;
-          });
-          double xr4[4], xi4[4];
-          replay_units<GROUP, NMAX, 4>(ar, ai, piv, rq, n, m, ur, ui, xr4, xi4);
-          static_for<0, 4>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            if (q0 + j >= R) return;
-            const double x_r = xr4[j], x_i = xi4[j];
-            const int gg = g + q0 + j;
-            const int c_begin = uniform(p.grp_ptr[gg]);
-            const int c_end = uniform(p.grp_ptr[gg + 1]);
-            for (int c = c_begin; c < c_end; ++c) {
-              const uint32_t crow = uniform(p.child_rowoff[c]);
-              const int cterm = uniform(p.child_term[c]);
-              double pr_ = 0.0, pi_ = 0.0;
-              if (m < n) {
-                const double2 s = *reinterpret_cast<const double2*>(lds + crow + mycol);
-                pr_ = s.x * x_r - s.y * x_i;
-                pi_ = s.x * x_i + s.y * x_r;
-              }
-              const double wc = a.w_src[cterm];
-              if constexpr (!WITH_A && !WITH_PAIRS) {
-                lre += wc * pr_;
-                lim += wc * pi_;
-              } else {
-                const double rr = group_sum<GROUP>(pr_);
-                const double ri = group_sum<GROUP>(pi_);
-                sre += wc * rr;
-                sim += wc * ri;
-                if (WITH_A && !zero) sabs_reg += fabs(wc) * sqrt(rr * rr + ri * ri);
-                if (WITH_PAIRS && writer && a.pair_det && !zero) {
-                  double cr = rr * dre - ri * dim, ci = rr * dim + ri * dre;
-#pragma unroll
-                  for (int h = 0; h < kPairFlavors; ++h) {
-                    if (h == f || h >= F) continue;
-                    const double tr = cr * Dpre_re[h] - ci * Dpre_im[h];
-                    ci = cr * Dpre_im[h] + ci * Dpre_re[h];
-                    cr = tr;
-                  }
-                  a.pair_det[((size_t)t * p.n_src + cterm) * p.n_snk + k] = make_double2(cr, ci);
-                }
-              }
+        for (int q = 0; q < R; ++q) {
+          // x = G^-1 e_r for this group's row r; lane m holds x[col]
+          double x_r, x_i;
+          replay_unit<GROUP, NMAX>(ar, ai, piv, uniform(p.grp_fr[g + q] & 0xff), n, m, ur, ui,
+                                   x_r, x_i);
+          const int gg = g + q;
+          const int c_begin = uniform(p.grp_ptr[gg]);
+          const int c_end = uniform(p.grp_ptr[gg + 1]);
+          for (int c = c_begin; c < c_end; ++c) {
+            const uint32_t crow = uniform(p.child_rowoff[c]);
+            const int cterm = uniform(p.child_term[c]);
+            double pr_ = 0.0, pi_ = 0.0;
+            if (m < n) {
+              const double2 s = *reinterpret_cast<const double2*>(lds + crow + mycol);
+              pr_ = s.x * x_r - s.y * x_i;
+              pi_ = s.x * x_i + s.y * x_r;
             }
-          });
-        }
-        if constexpr (!WITH_A && !WITH_PAIRS) {
-          sre = group_sum<GROUP>(lre);
-          sim = group_sum<GROUP>(lim);
+            const double rr = group_sum<GROUP>(pr_);
+            const double ri = group_sum<GROUP>(pi_);
+            const double wc = a.w_src[cterm];
+            sre += wc * rr;
+            sim += wc * ri;
+            if (WITH_A && !zero) sabs_reg += fabs(wc) * sqrt(rr * rr + ri * ri);
+            if (WITH_PAIRS && writer && a.pair_det && !zero) {
+              double cr = rr * dre - ri * dim, ci = rr * dim + ri * dre;
+#pragma unroll
+              for (int h = 0; h < kPairFlavors; ++h) {
+                if (h == f || h >= F) continue;
+                const double tr = cr * Dpre_re[h] - ci * Dpre_im[h];
+                ci = cr * Dpre_im[h] + ci * Dpre_re[h];
+                cr = tr;
+              }
+              a.pair_det[((size_t)t * p.n_src + cterm) * p.n_snk + k] = make_double2(cr, ci);
+            }
+          }
         }
         accre = zero ? 0.0 : dre * sre - dim * sim;
         accim = zero ? 0.0 : dre * sim + dim * sre;

@@ -20,7 +20,10 @@ import torch
 from . import _lib
 from ._lib import check, lib
 
-METHODS = {"plain": _lib.PLAIN_LU, "tree": _lib.UPDATE_TREE, "tree2": _lib.UPDATE_TREE2}
+METHODS = {"plain": _lib.PLAIN_LU, "tree": _lib.UPDATE_TREE, "tree2": _lib.UPDATE_TREE2,
+           # ablations: no pivoting (blocks of one size n <= 8)
+           "plain_unpivoted": _lib.PLAIN_LU_UNPIVOTED,
+           "tree_unpivoted": _lib.UPDATE_TREE_UNPIVOTED}
 POLICIES = {"R1": _lib.GREEDY_R1, "R2": _lib.GREEDY_R2}
 
 
@@ -62,11 +65,15 @@ class Terms:
 class Tree:
     """Update tree over source terms (host only)."""
 
-    def __init__(self, terms: Terms, policy: str = "R2"):
+    def __init__(self, terms: Terms, policy: str = "R2", share: bool = True):
+        """share=False: every child its own group (no shared solves; an
+        ablation)."""
         self.terms = terms
         self.policy = policy
+        self.share = share
+        flags = 0 if share else _lib.TREE_NO_SHARING
         h = ctypes.c_void_p()
-        check(lib().mhc_tree_build(terms.handle, POLICIES[policy], ctypes.byref(h)))
+        check(lib().mhc_tree_build(terms.handle, POLICIES[policy] | flags, ctypes.byref(h)))
         self._h = h
         self._destroy = lib().mhc_tree_destroy
 

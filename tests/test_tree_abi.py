@@ -153,6 +153,21 @@ def test_null_handles_and_destroy():
     assert b"policy" in L.mhc_last_error()
 
 
+def test_tree_without_sharing_has_one_group_per_child():
+    w = W.workload("mid", T=1, n_src=500, n_snk=10)
+    t = mhc.Terms(w.src, w.nf, w.M)
+    shared, alone = mhc.Tree(t), mhc.Tree(t, share=False)
+    a, b = shared.export(), alone.export()
+    for key in ("dom_order", "owner", "flav", "pos"):
+        assert np.array_equal(a[key], b[key])
+    sa, sb = shared.stats(), alone.stats()
+    assert sb["n_groups"] == sb["n_children"] == sa["n_children"]
+    assert sa["n_groups"] < sa["n_children"]
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.mhc_tree_build(t.handle, 3 | _lib.TREE_NO_SHARING, ctypes.byref(h)) == -1
+
+
 def test_batch_argument_errors_before_device_work():
     L = _lib.lib()
     L.mhc_batch_destroy(None)
