@@ -368,18 +368,20 @@ def main():
         # gradients for a random upstream gradient
         gC = torch.from_numpy(np.random.default_rng(0).standard_normal(w.T)
                               + 1j * np.random.default_rng(1).standard_normal(w.T)).to(dev)
-        for _ in range(args.warmup):
-            mhc.contract_backward(plan, S, ws, wk, gC)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.steps):
-            mhc.contract_backward(plan, S, ws, wk, gC)
-        e1.record()
-        torch.cuda.synchronize()
-        ms_b = e0.elapsed_time(e1) / args.steps
-        back = {"ms_per_step": ms_b, "det_pairs_per_s": w.n_pairs / (ms_b * 1e-3)}
+        back = {}
+        for bm in ("tree", "plain"):
+            for _ in range(args.warmup):
+                mhc.contract_backward(plan, S, ws, wk, gC, bm)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                mhc.contract_backward(plan, S, ws, wk, gC, bm)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_b = e0.elapsed_time(e1) / args.steps
+            back[bm] = {"ms_per_step": ms_b, "det_pairs_per_s": w.n_pairs / (ms_b * 1e-3)}
     two = None
     if len(set(w.nf)) == 1 and w.nf[0] <= 8:
         # the two-sided extension: sink terms in their own update tree

@@ -163,22 +163,28 @@ mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
                         const double* w_snk, void* C, double* A,
                         void* pair_det, void* stream);
 
-/* Adjoint of mhc_contract (both methods compute the same C; the adjoint
- * recomputes every pair's LU).  For an incoming gradient gC of a real loss
- * (PyTorch's convention for complex tensors):
+/* Adjoint of mhc_contract (every method computes the same C).  For an
+ * incoming gradient gC of a real loss (PyTorch's convention for complex
+ * tensors):
  *   gS[t][p][q] = gC[t] * conj(dC(t)/dS_t[p][q])      complex128 [T][M][M]
  *   g_wsrc[i]   = Re(sum_t gC[t] * conj(dC(t)/dw_i))   double [n_src]
  *   g_wsnk[j]   = Re(sum_t gC[t] * conj(dC(t)/dw'_j))  double [n_snk]
  * dC/dS follows from Jacobi's formula (d det G / dG[m][n] = det(G)
  * (G^-1)[n][m]) applied to every flavour block of every pair (Sec. 1
- * definitions); dC/dw from bilinearity.  Inputs as for mhc_contract; gC is
- * complex128 [T].  Any output pointer may be NULL (not written).  At most 4
- * flavour blocks; S_t and its gradient must fit in LDS together
- * (2 * M * (M + 1) * 16 bytes).  A flavour block with an exactly zero pivot
- * contributes nothing to gS and is counted (mhc_plan_status).  Device
- * scratch is allocated on the plan at the first call (and grown when T
- * grows). */
-mhc_status mhc_contract_backward(mhc_plan* plan, int32_t T, const void* S,
+ * definitions); dC/dw from bilinearity.  method MHC_PLAIN_LU recomputes
+ * every pair's LU and inverse; MHC_UPDATE_TREE factorises dominators only:
+ * a child's cofactor matrix is the dominator's updated by Sherman-Morrison
+ * (rank 1, Sec. 2), so the weighted sum over a dominator and its children
+ * is one scaled inverse plus one rank-1 term per group of siblings.
+ * Inputs as for mhc_contract; gC is complex128 [T].  Any output pointer may
+ * be NULL (not written).  At most 4 flavour blocks of one size n <= 8; S_t
+ * and its gradient must fit in LDS together (2 * M * (M + 1) * 16 bytes).
+ * A pair's flavour block with an exactly zero pivot (for MHC_UPDATE_TREE:
+ * every pair of a dominator whose block has one) is taken pair by pair, and
+ * a block that stays singular contributes nothing to gS and is counted
+ * (mhc_plan_status).  Device scratch is allocated on the plan at the first
+ * call (and grown when T grows). */
+mhc_status mhc_contract_backward(mhc_plan* plan, int32_t method, int32_t T, const void* S,
                                  const double* w_src, const double* w_snk,
                                  const void* gC, void* gS, double* g_wsrc,
                                  double* g_wsnk, void* stream);

@@ -30,131 +30,120 @@ namespace kern {
 
 constexpr int kMaxAdjFlavors = 4;
 
+// One source term against the lane's sink, pair by pair: the term's rows
+// are the row set `rowoff` with, in flavour fs, row rs replaced by the row
+// at byte offset srow (fs < 0: no replacement).  Pass 1 forms every block's
+// determinant; pass 2 refactorises each block, solves its N unit columns and
+// scatters coef * conj(X_f det_f) * conj(x_r[n]) into the LDS accumulator
+// (coef = gc * w_i * w_k).  Returns the pair determinant.  A block with an
+// exactly zero pivot is skipped in pass 2 and counted.
 template <int N>
-__global__ __launch_bounds__(kBlock, 2) void adjoint_kernel(AdjointArgs a) {
-  extern __shared__ double2 smem[];
-  const PlanView& p = a.plan;
-  const int t = blockIdx.y;
-  const int sb = blockIdx.x;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = uniform(threadIdx.x / kWave);
-  const int MM = p.M * p.M;
-  const int LL = p.M * lds_row(p.M);
-  double2* Sl = smem;            // S_t (padded rows)
-  double2* gl = smem + LL;       // grad S_t accumulator, same layout
-  const double2* St = a.S + (size_t)t * MM;
-  stage_slice(St, Sl, p.M, kBlock);
-  for (int e = threadIdx.x; e < LL; e += kBlock) gl[e] = make_double2(0.0, 0.0);
-  __syncthreads();
-  const char* lds = reinterpret_cast<const char*>(Sl);
-  char* glds = reinterpret_cast<char*>(gl);
-
-  const int k = sb * kWave + lane;
-  const bool valid = k < p.n_snk;
-  const double wk = valid ? a.w_snk[k] : 0.0;
-  const double2 gc = a.gC[t];
+__device__ __forceinline__ double2 member_adjoint(const PlanView& p, const char* lds, char* glds,
+                                                  const uint32_t* rowoff, int fs, int rs,
+                                                  uint32_t srow, int k, bool valid, double2 gc,
+                                                  double cw, uint32_t& n_singular) {
   const int F = p.F;
-  const int sn = p.sn;
-  double acc_wk = 0.0;
-  uint32_t n_singular = 0;
-
-  for (int i = wave; i < p.n_src; i += kWavesPerBlock) {
-    const uint32_t* rowoff_i = p.src_rowoff + (size_t)i * sn;
-    const double wi = a.w_src[i];
-    // pass 1: the determinant of every flavour block
-    double dre[kMaxAdjFlavors], dim[kMaxAdjFlavors];
-    bool zero[kMaxAdjFlavors];
+  double dre[kMaxAdjFlavors], dim[kMaxAdjFlavors];
 #pragma unroll
-    for (int f = 0; f < kMaxAdjFlavors; ++f) {
-      dre[f] = 1.0;
-      dim[f] = 0.0;
-      zero[f] = false;
-      if (f < F) {
-        const int o = p.off[f];
-        uint32_t ro[N], co[N];
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-          ro[n] = rowoff_i[o + n];
-          co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + k];
-        }
-        double gr[N][N], gi[N][N];
-        int perm[N];
-        gather<N>(lds, ro, co, gr, gi);
-        lu<N, true>(gr, gi, dre[f], dim[f], perm, zero[f]);
-      }
-    }
-    double d_re = 1.0, d_im = 0.0;
-#pragma unroll
-    for (int f = 0; f < kMaxAdjFlavors; ++f) {
-      const double tr = d_re * dre[f] - d_im * dim[f];
-      d_im = d_re * dim[f] + d_im * dre[f];
-      d_re = tr;
-    }
-    // weights: Re(gc * conj(d))
-    const double val = valid ? gc.x * d_re + gc.y * d_im : 0.0;
-    acc_wk += wi * val;
-    const double s_i = wave_sum(wk * val);
-    if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + i) * a.n_sblk + sb] = s_i;
-
-    // pass 2: grad S.  coef = gc * w_i * w_k (0 on padded lanes)
-    const double cw = wi * wk;
-    const double cre = gc.x * cw, cim = gc.y * cw;
-#pragma unroll
-    for (int f = 0; f < kMaxAdjFlavors; ++f) {
-      if (f >= F) continue;
-      // X_f = prod of the other blocks' determinants
-      double xre = 1.0, xim = 0.0;
-#pragma unroll
-      for (int g = 0; g < kMaxAdjFlavors; ++g) {
-        if (g == f) continue;
-        const double tr = xre * dre[g] - xim * dim[g];
-        xim = xre * dim[g] + xim * dre[g];
-        xre = tr;
-      }
-      // b = coef * conj(X_f det_f)
-      const double pre = xre * dre[f] - xim * dim[f];
-      const double pim = xre * dim[f] + xim * dre[f];
-      const double bre = cre * pre + cim * pim;
-      const double bim = cim * pre - cre * pim;
+  for (int f = 0; f < kMaxAdjFlavors; ++f) {
+    dre[f] = 1.0;
+    dim[f] = 0.0;
+    if (f < F) {
       const int o = p.off[f];
       uint32_t ro[N], co[N];
 #pragma unroll
       for (int n = 0; n < N; ++n) {
-        ro[n] = rowoff_i[o + n];
+        ro[n] = (f == fs && n == rs) ? srow : rowoff[o + n];
         co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + k];
       }
       double gr[N][N], gi[N][N];
       int perm[N];
-      double ddr, ddi;
       bool z;
       gather<N>(lds, ro, co, gr, gi);
-      lu<N, true>(gr, gi, ddr, ddi, perm, z);
-      if (z) {
-        // det_f = 0 exactly: its adjugate is not formed from an inverse;
-        // the block's contribution is skipped and counted
-        if (valid) ++n_singular;
-        continue;
-      }
+      lu<N, false>(gr, gi, dre[f], dim[f], perm, z);
+    }
+  }
+  double d_re = 1.0, d_im = 0.0;
 #pragma unroll
-      for (int r = 0; r < N; ++r) {
-        double xr[N], xi[N];
-        solve_unit<N>(gr, gi, perm, r, xr, xi);
+  for (int f = 0; f < kMaxAdjFlavors; ++f) {
+    const double tr = d_re * dre[f] - d_im * dim[f];
+    d_im = d_re * dim[f] + d_im * dre[f];
+    d_re = tr;
+  }
+  const double cre = gc.x * cw, cim = gc.y * cw;
 #pragma unroll
-        for (int n = 0; n < N; ++n) {
-          // grad S[a_i^{f,r}][a_k^{f,n}] += b * conj(x[n])
-          const double vr = bre * xr[n] + bim * xi[n];
-          const double vi = bim * xr[n] - bre * xi[n];
-          double* dst = reinterpret_cast<double*>(glds + ro[r] + co[n]);
-          if (valid) {
-            atomicAdd(dst, vr);
-            atomicAdd(dst + 1, vi);
-          }
+  for (int f = 0; f < kMaxAdjFlavors; ++f) {
+    if (f >= F) continue;
+    // X_f = prod of the other blocks' determinants
+    double xre = 1.0, xim = 0.0;
+#pragma unroll
+    for (int g = 0; g < kMaxAdjFlavors; ++g) {
+      if (g == f) continue;
+      const double tr = xre * dre[g] - xim * dim[g];
+      xim = xre * dim[g] + xim * dre[g];
+      xre = tr;
+    }
+    // b = coef * conj(X_f det_f)
+    const double pre = xre * dre[f] - xim * dim[f];
+    const double pim = xre * dim[f] + xim * dre[f];
+    const double bre = cre * pre + cim * pim;
+    const double bim = cim * pre - cre * pim;
+    const int o = p.off[f];
+    uint32_t ro[N], co[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      ro[n] = (f == fs && n == rs) ? srow : rowoff[o + n];
+      co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + k];
+    }
+    double gr[N][N], gi[N][N];
+    int perm[N];
+    double ddr, ddi;
+    bool z;
+    gather<N>(lds, ro, co, gr, gi);
+    lu<N, true>(gr, gi, ddr, ddi, perm, z);
+    if (z) {
+      // det_f = 0 exactly: its adjugate is not formed from an inverse;
+      // the block's contribution is skipped and counted
+      if (valid) ++n_singular;
+      continue;
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      double xr[N], xi[N];
+      solve_unit<N>(gr, gi, perm, r, xr, xi);
+#pragma unroll
+      for (int n = 0; n < N; ++n) {
+        // grad S[row r][col n] += b * conj(x[n])
+        const double vr = bre * xr[n] + bim * xi[n];
+        const double vi = bim * xr[n] - bre * xi[n];
+        double* dst = reinterpret_cast<double*>(glds + ro[r] + co[n]);
+        if (valid) {
+          atomicAdd(dst, vr);
+          atomicAdd(dst + 1, vi);
         }
       }
     }
   }
+  return make_double2(d_re, d_im);
+}
 
-  // per-lane sink-weight partials, waves combined in a fixed order
+// Stages S_t and clears the grad S_t accumulator (both padded rows).
+__device__ __forceinline__ void adjoint_stage(const AdjointArgs& a, int t, double2* smem) {
+  const PlanView& p = a.plan;
+  const int LL = p.M * lds_row(p.M);
+  stage_slice(a.S + (size_t)t * p.M * p.M, smem, p.M, kBlock);
+  double2* gl = smem + LL;
+  for (int e = threadIdx.x; e < LL; e += kBlock) gl[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+}
+
+// Per-lane sink-weight partials (waves combined in a fixed order), the
+// singular-block counter and the workgroup's grad S_t partial.
+__device__ __forceinline__ void adjoint_finish(const AdjointArgs& a, int t, int sb, double acc_wk,
+                                               uint32_t n_singular, double2* smem) {
+  const PlanView& p = a.plan;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = uniform(threadIdx.x / kWave);
   __shared__ double red[kWavesPerBlock][kWave];
   red[wave][lane] = acc_wk;
   if (a.singular) {
@@ -170,8 +159,286 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_kernel(AdjointArgs a) {
     for (int w = 0; w < kWavesPerBlock; ++w) v += red[w][threadIdx.x];
     a.part_wsnk[(size_t)t * p.n_snk_pad + sb * kWave + threadIdx.x] = v;
   }
+  const int MM = p.M * p.M;
+  const double2* gl = smem + p.M * lds_row(p.M);
   double2* dst = a.part_gS + ((size_t)t * a.n_sblk + sb) * MM;
   for (int e = threadIdx.x; e < MM; e += kBlock) dst[e] = gl[(e / p.M) * lds_row(p.M) + e % p.M];
+}
+
+// Plain adjoint: every source term, pair by pair.
+template <int N>
+__global__ __launch_bounds__(kBlock, 2) void adjoint_kernel(AdjointArgs a) {
+  extern __shared__ double2 smem[];
+  const PlanView& p = a.plan;
+  const int t = blockIdx.y;
+  const int sb = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = uniform(threadIdx.x / kWave);
+  adjoint_stage(a, t, smem);
+  const char* lds = reinterpret_cast<const char*>(smem);
+  char* glds = reinterpret_cast<char*>(smem + p.M * lds_row(p.M));
+  const int k = sb * kWave + lane;
+  const bool valid = k < p.n_snk;
+  const double wk = valid ? a.w_snk[k] : 0.0;
+  const double2 gc = a.gC[t];
+  double acc_wk = 0.0;
+  uint32_t n_singular = 0;
+  for (int i = wave; i < p.n_src; i += kWavesPerBlock) {
+    const double wi = a.w_src[i];
+    const double2 d = member_adjoint<N>(p, lds, glds, p.src_rowoff + (size_t)i * p.sn, -1, -1,
+                                        0u, k, valid, gc, wi * wk, n_singular);
+    // weights: Re(gc * conj(d))
+    const double val = valid ? gc.x * d.x + gc.y * d.y : 0.0;
+    acc_wk += wi * val;
+    const double s_i = wave_sum(wk * val);
+    if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + i) * a.n_sblk + sb] = s_i;
+  }
+  adjoint_finish(a, t, sb, acc_wk, n_singular, smem);
+}
+
+// Update-tree adjoint: one (dominator, sink) at a time.  With G the
+// dominator's block f, x_m = G^-1 e_m, and the child c of flavour f that
+// replaces row r by s_c (z_c = s_c^T G^-1, rho_c = z_c[r]), the cofactor
+// matrix of the child is rho_c det G G^-T - det G (z_c - e_r) x_r^T
+// (Sherman-Morrison); its row r is det G x_r^T and belongs to the new row
+// s_c.  Summed over the partition with the weights, block f's derivative
+// on the dominator's rows is
+//   X_f det G_f (W (G^-1)^T - sum_groups Z_r x_r^T),  W = w_d + sum_c w_c rho_c,
+// Z_r = sum_{c in group r} w_c z_c (children of other flavours enter W
+// through their own rho_c; the rank-1 terms vanish on row r), and each
+// child adds w_c X_f det G_f x_r to its own row.  Pass A factorises the
+// blocks and forms W; pass B refactorises each block, solves its N unit
+// columns, the children's row vectors, and scatters.  A lane whose
+// dominator block has an exactly zero pivot takes every member pair by pair.
+template <int N>
+__global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) {
+  extern __shared__ double2 smem[];
+  const PlanView& p = a.plan;
+  const int t = blockIdx.y;
+  const int sb = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = uniform(threadIdx.x / kWave);
+  adjoint_stage(a, t, smem);
+  const char* lds = reinterpret_cast<const char*>(smem);
+  char* glds = reinterpret_cast<char*>(smem + p.M * lds_row(p.M));
+  const int k = sb * kWave + lane;
+  const bool valid = k < p.n_snk;
+  const double wk = valid ? a.w_snk[k] : 0.0;
+  const double2 gc = a.gC[t];
+  const int F = p.F;
+  const int sn = p.sn;
+  double acc_wk = 0.0;
+  uint32_t n_singular = 0;
+
+  for (int d = wave; d < p.n_dom; d += kWavesPerBlock) {
+    const int term_d = uniform(p.dom_term[d]);
+    const double wd = a.w_src[term_d];
+    const uint32_t* rowoff_d = p.dom_rowoff + (size_t)d * sn;
+    const int g_begin = uniform(p.dom_grp[d]);
+    const int g_end = uniform(p.dom_grp[d + 1]);
+
+    // pass A: block determinants and W
+    double dre[kMaxAdjFlavors], dim[kMaxAdjFlavors];
+    double Wre = wd, Wim = 0.0;
+    bool bad = false;
+    int g = g_begin;
+#pragma unroll
+    for (int f = 0; f < kMaxAdjFlavors; ++f) {
+      dre[f] = 1.0;
+      dim[f] = 0.0;
+      if (f >= F) continue;
+      const int o = p.off[f];
+      uint32_t ro[N], co[N];
+#pragma unroll
+      for (int n = 0; n < N; ++n) {
+        ro[n] = rowoff_d[o + n];
+        co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + k];
+      }
+      double gr[N][N], gi[N][N];
+      int perm[N];
+      bool z;
+      gather<N>(lds, ro, co, gr, gi);
+      lu<N, true>(gr, gi, dre[f], dim[f], perm, z);
+      bad = bad || z;
+      for (; g < g_end && uniform(p.grp_fr[g] >> 8) == f; ++g) {
+        const int r = uniform(p.grp_fr[g] & 0xff);
+        double xr[N], xi[N];
+        solve_unit<N>(gr, gi, perm, r, xr, xi);
+        for (int c = uniform(p.grp_ptr[g]); c < uniform(p.grp_ptr[g + 1]); ++c) {
+          const uint32_t crow = uniform(p.child_rowoff[c]);
+          const double wc = a.w_src[uniform(p.child_term[c])];
+          double rr = 0.0, ri = 0.0;
+#pragma unroll
+          for (int n = 0; n < N; ++n) {
+            const double2 sv = *reinterpret_cast<const double2*>(lds + crow + co[n]);
+            rr += sv.x * xr[n] - sv.y * xi[n];
+            ri += sv.x * xi[n] + sv.y * xr[n];
+          }
+          Wre += wc * rr;
+          Wim += wc * ri;
+        }
+      }
+    }
+    double Dre = 1.0, Dim = 0.0;
+#pragma unroll
+    for (int f = 0; f < kMaxAdjFlavors; ++f) {
+      const double tr = Dre * dre[f] - Dim * dim[f];
+      Dim = Dre * dim[f] + Dim * dre[f];
+      Dre = tr;
+    }
+    const bool fast = valid && !bad;
+    // weights of the sink (all members) and of the dominator
+    if (fast) {
+      const double pr = Dre * Wre - Dim * Wim, pi = Dre * Wim + Dim * Wre;
+      acc_wk += gc.x * pr + gc.y * pi;
+    }
+    {
+      const double val = fast ? gc.x * Dre + gc.y * Dim : 0.0;
+      const double s_d = wave_sum(wk * val);
+      if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + term_d) * a.n_sblk + sb] = s_d;
+    }
+
+    // pass B: scatter, block by block
+    g = g_begin;
+#pragma unroll
+    for (int f = 0; f < kMaxAdjFlavors; ++f) {
+      if (f >= F) continue;
+      const int o = p.off[f];
+      int g_f_end = g;
+      while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
+      // B = gc * w_k * conj(X_f det_f) = gc * w_k * conj(D)
+      const double bre = wk * (gc.x * Dre + gc.y * Dim);
+      const double bim = wk * (gc.y * Dre - gc.x * Dim);
+      uint32_t ro[N], co[N];
+#pragma unroll
+      for (int n = 0; n < N; ++n) {
+        ro[n] = rowoff_d[o + n];
+        co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + k];
+      }
+      double gr[N][N], gi[N][N];
+      int perm[N];
+      double ddr, ddi;
+      bool z;
+      gather<N>(lds, ro, co, gr, gi);
+      lu<N, true>(gr, gi, ddr, ddi, perm, z);
+      uint32_t prow[N];
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        uint32_t v = ro[0];
+#pragma unroll
+        for (int j = 1; j < N; ++j)
+          if (perm[m] == j) v = ro[j];
+        prow[m] = v;
+      }
+      int gg = g;
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        double xr[N], xi[N];
+        solve_unit<N>(gr, gi, perm, m, xr, xi);
+        // W (G^-1)^T: row m gets W x_m[n]; value v -> grad += B * conj(v)
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+          const double vr = Wre * xr[n] - Wim * xi[n];
+          const double vi = Wre * xi[n] + Wim * xr[n];
+          double* dst = reinterpret_cast<double*>(glds + ro[m] + co[n]);
+          if (fast) {
+            atomicAdd(dst, bre * vr + bim * vi);
+            atomicAdd(dst + 1, bim * vr - bre * vi);
+          }
+        }
+        // the group that changes row m, if any (groups are sorted by row)
+        if (gg < g_f_end && uniform(p.grp_fr[gg] & 0xff) == m) {
+          double Zr[N], Zi[N];
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            Zr[j] = 0.0;
+            Zi[j] = 0.0;
+          }
+          for (int c = uniform(p.grp_ptr[gg]); c < uniform(p.grp_ptr[gg + 1]); ++c) {
+            const uint32_t crow = uniform(p.child_rowoff[c]);
+            const int cterm = uniform(p.child_term[c]);
+            const double wc = a.w_src[cterm];
+            double br[N], bi[N];
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+              const double2 sv = *reinterpret_cast<const double2*>(lds + crow + co[n]);
+              br[n] = sv.x;
+              bi[n] = sv.y;
+            }
+            solve_row<N>(gr, gi, br, bi);       // z_c, as b with z[perm[j]] = b[j]
+            // rho_c = z_c[m]
+            double rr = 0.0, ri = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+              if (perm[j] == m) {
+                rr = br[j];
+                ri = bi[j];
+              }
+            // the child's source weight: sum over sinks of w_k Re(gc conj(rho D))
+            const double cr = rr * Dre - ri * Dim, ci = rr * Dim + ri * Dre;
+            const double s_c = wave_sum(fast ? wk * (gc.x * cr + gc.y * ci) : 0.0);
+            if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + cterm) * a.n_sblk + sb] = s_c;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+              Zr[j] += wc * br[j];
+              Zi[j] += wc * bi[j];
+            }
+            // the child's own row: w_c x_m[n] at (new row, column n)
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+              double* dst = reinterpret_cast<double*>(glds + crow + co[n]);
+              if (fast) {
+                atomicAdd(dst, wc * (bre * xr[n] + bim * xi[n]));
+                atomicAdd(dst + 1, wc * (bim * xr[n] - bre * xi[n]));
+              }
+            }
+          }
+          // - Z_r x_r^T on the dominator's rows (Z in pivot order: entry j
+          // is original row perm[j])
+#pragma unroll
+          for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+              const double vr = -(Zr[j] * xr[n] - Zi[j] * xi[n]);
+              const double vi = -(Zr[j] * xi[n] + Zi[j] * xr[n]);
+              double* dst = reinterpret_cast<double*>(glds + prow[j] + co[n]);
+              if (fast) {
+                atomicAdd(dst, bre * vr + bim * vi);
+                atomicAdd(dst + 1, bim * vr - bre * vi);
+              }
+            }
+          ++gg;
+        }
+      }
+      g = g_f_end;
+    }
+
+    // a dominator block with an exactly zero pivot: every member pair by pair
+    const bool need = valid && bad;
+    if (__builtin_amdgcn_ballot_w64(need) != 0) {
+      double2 dd = member_adjoint<N>(p, lds, glds, rowoff_d, -1, -1, 0u, k, need, gc, wd * wk,
+                                     n_singular);
+      double val = need ? gc.x * dd.x + gc.y * dd.y : 0.0;
+      acc_wk += wd * val;
+      double s_i = wave_sum(wk * val);
+      if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + term_d) * a.n_sblk + sb] += s_i;
+      for (int gg = g_begin; gg < g_end; ++gg) {
+        const int fs = uniform(p.grp_fr[gg] >> 8), rs = uniform(p.grp_fr[gg] & 0xff);
+        for (int c = uniform(p.grp_ptr[gg]); c < uniform(p.grp_ptr[gg + 1]); ++c) {
+          const uint32_t crow = uniform(p.child_rowoff[c]);
+          const int cterm = uniform(p.child_term[c]);
+          const double wc = a.w_src[cterm];
+          dd = member_adjoint<N>(p, lds, glds, rowoff_d, fs, rs, crow, k, need, gc, wc * wk,
+                                 n_singular);
+          val = need ? gc.x * dd.x + gc.y * dd.y : 0.0;
+          acc_wk += wc * val;
+          s_i = wave_sum(wk * val);
+          if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + cterm) * a.n_sblk + sb] += s_i;
+        }
+      }
+    }
+  }
+  adjoint_finish(a, t, sb, acc_wk, n_singular, smem);
 }
 
 // grad S[t][e] = sum over sink blocks of the partials (fixed order)
@@ -209,28 +476,32 @@ __global__ __launch_bounds__(kBlock) void reduce_w(const double* part_src, const
 }
 
 template <int N>
-static hipError_t launch_adj_n(const AdjointArgs& a, hipStream_t s) {
+static hipError_t launch_adj_n(const AdjointArgs& a, bool tree, hipStream_t s) {
   dim3 grid(a.n_sblk, a.T);
   size_t lds = 2 * lds_slice_bytes(a.plan.M);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adjoint_kernel<N>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* fn = tree ? reinterpret_cast<const void*>(&adjoint_tree_kernel<N>)
+                        : reinterpret_cast<const void*>(&adjoint_kernel<N>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adjoint_kernel<N>, grid, dim3(kBlock), lds, s, a);
+  if (tree)
+    hipLaunchKernelGGL(adjoint_tree_kernel<N>, grid, dim3(kBlock), lds, s, a);
+  else
+    hipLaunchKernelGGL(adjoint_kernel<N>, grid, dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const AdjointArgs& a, int n, double2* gS, double* g_wsrc,
+hipError_t launch_adjoint(const AdjointArgs& a, int n, bool tree, double2* gS, double* g_wsrc,
                           double* g_wsnk, hipStream_t s) {
   hipError_t e;
   switch (n) {
-    case 1: e = launch_adj_n<1>(a, s); break;
-    case 2: e = launch_adj_n<2>(a, s); break;
-    case 3: e = launch_adj_n<3>(a, s); break;
-    case 4: e = launch_adj_n<4>(a, s); break;
-    case 5: e = launch_adj_n<5>(a, s); break;
-    case 6: e = launch_adj_n<6>(a, s); break;
-    case 7: e = launch_adj_n<7>(a, s); break;
-    case 8: e = launch_adj_n<8>(a, s); break;
+    case 1: e = launch_adj_n<1>(a, tree, s); break;
+    case 2: e = launch_adj_n<2>(a, tree, s); break;
+    case 3: e = launch_adj_n<3>(a, tree, s); break;
+    case 4: e = launch_adj_n<4>(a, tree, s); break;
+    case 5: e = launch_adj_n<5>(a, tree, s); break;
+    case 6: e = launch_adj_n<6>(a, tree, s); break;
+    case 7: e = launch_adj_n<7>(a, tree, s); break;
+    case 8: e = launch_adj_n<8>(a, tree, s); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;

@@ -95,6 +95,9 @@ hipError_t launch_batch_lane(const BatchArgs& b, int n, bool tree, bool with_a, 
 hipError_t launch_batch_wide(const BatchArgs& b, int nmax, bool tree, bool with_a, int grid,
                              size_t lds, hipStream_t s);
 int wide_bucket(int nmax);
+// Threads per workgroup of a group kernel (512 or 1024) for a bucket and
+// the LDS bytes one slice of S takes.
+int wide_block(int nmax, bool tree, size_t lds);
 // C_j[t] for each entry (job, t) of jt (n entries).
 hipError_t launch_batch_reduce(const ContractArgs* jobs, const int2* jt, int n, hipStream_t s);
 
@@ -117,10 +120,10 @@ struct AdjointArgs {
   int T, n_sblk;
 };
 
-// Enqueues the adjoint of the plain contraction and the fixed-order
-// reductions into gS [T][M][M], g_wsrc [n_src], g_wsnk [n_snk] (any output
-// may be null).
-hipError_t launch_adjoint(const AdjointArgs& a, int n, double2* gS, double* g_wsrc,
+// Enqueues the adjoint (pair by pair, or by the source update tree) and the
+// fixed-order reductions into gS [T][M][M], g_wsrc [n_src], g_wsnk [n_snk]
+// (any output may be null).
+hipError_t launch_adjoint(const AdjointArgs& a, int n, bool tree, double2* gS, double* g_wsrc,
                           double* g_wsnk, hipStream_t s);
 
 }  // namespace kern

@@ -287,6 +287,36 @@ __device__ __forceinline__ void solve_unit(const double (&gr)[N][N],
   }
 }
 
+// b with h^T G^-1 = b^T P (that is (h^T G^-1)[perm[m]] = b[m]) from the
+// factors of lu<N, true> (P G = L U, diagonal holding 1/U_mm): a^T U = h^T,
+// then b^T L = a^T.  (br, bi) holds h on entry.
+template <int N>
+__device__ __forceinline__ void solve_row(const double (&gr)[N][N], const double (&gi)[N][N],
+                                          double (&br)[N], double (&bi)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double tr = br[j], ti = bi[j];
+#pragma unroll
+    for (int i = 0; i < j; ++i) {
+      tr = tr - br[i] * gr[i][j] + bi[i] * gi[i][j];
+      ti = ti - br[i] * gi[i][j] - bi[i] * gr[i][j];
+    }
+    br[j] = tr * gr[j][j] - ti * gi[j][j];
+    bi[j] = tr * gi[j][j] + ti * gr[j][j];
+  }
+#pragma unroll
+  for (int j = N - 2; j >= 0; --j) {
+    double tr = br[j], ti = bi[j];
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      tr = tr - br[i] * gr[i][j] + bi[i] * gi[i][j];
+      ti = ti - br[i] * gi[i][j] - bi[i] * gr[i][j];
+    }
+    br[j] = tr;
+    bi[j] = ti;
+  }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

@@ -395,7 +395,7 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   return MHC_OK;
 }
 
-mhc_status mhc_contract_backward(mhc_plan* pl, int32_t T, const void* S,
+mhc_status mhc_contract_backward(mhc_plan* pl, int32_t method, int32_t T, const void* S,
                                  const double* w_src, const double* w_snk,
                                  const void* gC, void* gS, double* g_wsrc,
                                  double* g_wsnk, void* stream) {
@@ -404,6 +404,8 @@ mhc_status mhc_contract_backward(mhc_plan* pl, int32_t T, const void* S,
     return fail(MHC_E_ARG, "mhc_contract_backward: NULL input buffer");
   if (T < 1 || T > 65535)
     return fail(MHC_E_ARG, "mhc_contract_backward: T outside [1, 65535]");
+  if (method != MHC_PLAIN_LU && method != MHC_UPDATE_TREE)
+    return fail(MHC_E_ARG, "mhc_contract_backward: method must be MHC_PLAIN_LU or MHC_UPDATE_TREE");
   if (pl->F > 4)
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_contract_backward: more than 4 flavour blocks");
@@ -453,7 +455,8 @@ mhc_status mhc_contract_backward(mhc_plan* pl, int32_t T, const void* S,
   a.singular = pl->singular;
   a.T = T;
   a.n_sblk = n_sblk;
-  e = mhc::kern::launch_adjoint(a, pl->n, static_cast<double2*>(gS), g_wsrc, g_wsnk, s);
+  e = mhc::kern::launch_adjoint(a, pl->n, method == MHC_UPDATE_TREE, static_cast<double2*>(gS),
+                                g_wsrc, g_wsnk, s);
   if (e != hipSuccess) return hip_fail(e, "mhc_contract_backward/launch");
   return MHC_OK;
 }

@@ -34,8 +34,11 @@
 namespace mhc {
 namespace kern {
 
+// Workgroup sizes: 512 threads, or 1024 where one slice of S fills most of
+// the LDS (one workgroup per CU) and the kernel fits in 128 VGPRs, so that
+// four waves per SIMD hide the broadcast latencies of the elimination.
 constexpr int kWideBlock = 512;
-constexpr int kWideWaves = kWideBlock / kWave;
+constexpr int kWideBlockBig = 1024;
 
 // A double moved across lanes by a DPP row rotation (within each row of 16
 // lanes): lane i receives lane (i + R) mod 16 of its row.
@@ -230,7 +233,7 @@ __device__ __forceinline__ void block_det_direct(const char* lds, uint32_t myrow
 }
 
 // One tile (slice t, chunk) of a job, as lane_tile for one matrix per lane.
-template <int GROUP, int NMAX, bool TREE, int MODE>
+template <int GROUP, int NMAX, bool TREE, int MODE, int WB>
 __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chunk,
                                           double2* smem) {
   constexpr bool WITH_A = (MODE & 1) != 0;
@@ -244,7 +247,8 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
   const int gsel = lane / GROUP;       // which sink of the wave
   const int MM = p.M * p.M;
   const double2* St = a.S + (size_t)t * MM;
-  stage_slice(St, smem, p.M, kWideBlock);
+  constexpr int kWaves = WB / kWave;
+  stage_slice(St, smem, p.M, WB);
   __syncthreads();
   const char* lds = reinterpret_cast<const char*>(smem);
 
@@ -254,7 +258,7 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
   const int sn = p.sn;
 
   for (int item = chunk + a.n_blk_t * wave; item < a.n_items;
-       item += a.n_blk_t * kWideWaves) {
+       item += a.n_blk_t * kWaves) {
     const int d = uniform(item / a.n_sblk);
     const int sb = uniform(item - d * a.n_sblk);
     const int k = sb * SPW + gsel;
@@ -446,7 +450,7 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
     }
   }
 
-  __shared__ double red[kWideWaves][3];
+  __shared__ double red[kWaves][3];
   const double s0 = wave_sum(acc_re), s1 = wave_sum(acc_im);
   const double s2 = WITH_A ? wave_sum(acc_a) : 0.0;
   if (lane == 0) {
@@ -464,37 +468,59 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
   if (threadIdx.x < 3) {
     double v = 0.0;
 #pragma unroll
-    for (int w = 0; w < kWideWaves; ++w) v += red[w][threadIdx.x];
+    for (int w = 0; w < kWaves; ++w) v += red[w][threadIdx.x];
     a.partial[((size_t)t * a.n_blk_t + chunk) * 3 + threadIdx.x] = v;
   }
 }
 
-template <int GROUP, int NMAX, bool TREE, int MODE>
-__global__ __launch_bounds__(kWideBlock) void contract_wide_kernel(ContractArgs a) {
+template <int GROUP, int NMAX, bool TREE, int MODE, int WB>
+__global__ __launch_bounds__(WB) void contract_wide_kernel(ContractArgs a) {
   extern __shared__ double2 smem[];
-  wide_tile<GROUP, NMAX, TREE, MODE>(a, blockIdx.y, blockIdx.x, smem);
+  wide_tile<GROUP, NMAX, TREE, MODE, WB>(a, blockIdx.y, blockIdx.x, smem);
 }
 
-template <int GROUP, int NMAX, bool TREE, int MODE>
-__global__ __launch_bounds__(kWideBlock) void batch_wide_kernel(BatchArgs b) {
+template <int GROUP, int NMAX, bool TREE, int MODE, int WB>
+__global__ __launch_bounds__(WB) void batch_wide_kernel(BatchArgs b) {
   extern __shared__ double2 smem[];
   for (int i = blockIdx.x; i < b.n_tiles; i += gridDim.x) {
     const int4 tl = b.tiles[i];
-    wide_tile<GROUP, NMAX, TREE, MODE>(b.jobs[tl.x], tl.y, tl.z, smem);
+    wide_tile<GROUP, NMAX, TREE, MODE, WB>(b.jobs[tl.x], tl.y, tl.z, smem);
   }
+}
+
+// 1024-thread workgroups where they measured faster on the batched and
+// large workloads: every plain bucket, and the tree's (16, 8) and (16, 12)
+// (the larger tree buckets spill too much in 128 VGPRs); only when the
+// slice needs over 80 KB of LDS, and not for the test-hook modes.
+constexpr bool big_block_allowed(int nmax, bool tree, int mode) {
+  return (mode & 2) == 0 && (!tree || nmax <= 12);
+}
+
+int wide_block(int nmax, bool tree, size_t lds) {
+  if (lds <= 80 * 1024) return kWideBlock;
+  return big_block_allowed(wide_bucket(nmax), tree, 0) ? kWideBlockBig : kWideBlock;
+}
+
+template <int GROUP, int NMAX, bool TREE, int MODE, int WB>
+static hipError_t launch_wide_wb(const ContractArgs& a, size_t lds, hipStream_t s) {
+  dim3 grid(a.n_blk_t, a.T);
+  hipError_t e = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&contract_wide_kernel<GROUP, NMAX, TREE, MODE, WB>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((contract_wide_kernel<GROUP, NMAX, TREE, MODE, WB>), grid, dim3(WB), lds,
+                     s, a);
+  return hipGetLastError();
 }
 
 template <int GROUP, int NMAX, bool TREE, int MODE>
 static hipError_t launch_wide_one(const ContractArgs& a, hipStream_t s) {
-  dim3 grid(a.n_blk_t, a.T);
   const size_t lds = lds_slice_bytes(a.plan.M);
-  hipError_t e = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&contract_wide_kernel<GROUP, NMAX, TREE, MODE>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((contract_wide_kernel<GROUP, NMAX, TREE, MODE>), grid, dim3(kWideBlock), lds,
-                     s, a);
-  return hipGetLastError();
+  if constexpr (big_block_allowed(NMAX, TREE, MODE)) {
+    if (wide_block(NMAX, TREE, lds) == kWideBlockBig)
+      return launch_wide_wb<GROUP, NMAX, TREE, MODE, kWideBlockBig>(a, lds, s);
+  }
+  return launch_wide_wb<GROUP, NMAX, TREE, MODE, kWideBlock>(a, lds, s);
 }
 
 template <int GROUP, int NMAX>
@@ -508,15 +534,24 @@ static hipError_t launch_wide_n(const ContractArgs& a, bool tree, bool diag, hip
 
 int wide_sinks_per_wave(int nmax) { return nmax <= 16 ? kWave / 16 : kWave / 32; }
 
-template <int GROUP, int NMAX, bool TREE, int MODE>
-static hipError_t launch_batch_wide_m(const BatchArgs& b, int grid, size_t lds, hipStream_t s) {
+template <int GROUP, int NMAX, bool TREE, int MODE, int WB>
+static hipError_t launch_batch_wide_wb(const BatchArgs& b, int grid, size_t lds, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&batch_wide_kernel<GROUP, NMAX, TREE, MODE>),
+      reinterpret_cast<const void*>(&batch_wide_kernel<GROUP, NMAX, TREE, MODE, WB>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((batch_wide_kernel<GROUP, NMAX, TREE, MODE>), dim3(grid), dim3(kWideBlock),
+  hipLaunchKernelGGL((batch_wide_kernel<GROUP, NMAX, TREE, MODE, WB>), dim3(grid), dim3(WB),
                      lds, s, b);
   return hipGetLastError();
+}
+
+template <int GROUP, int NMAX, bool TREE, int MODE>
+static hipError_t launch_batch_wide_m(const BatchArgs& b, int grid, size_t lds, hipStream_t s) {
+  if constexpr (big_block_allowed(NMAX, TREE, MODE)) {
+    if (wide_block(NMAX, TREE, lds) == kWideBlockBig)
+      return launch_batch_wide_wb<GROUP, NMAX, TREE, MODE, kWideBlockBig>(b, grid, lds, s);
+  }
+  return launch_batch_wide_wb<GROUP, NMAX, TREE, MODE, kWideBlock>(b, grid, lds, s);
 }
 
 template <int GROUP, int NMAX>

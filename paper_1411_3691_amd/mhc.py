@@ -212,11 +212,15 @@ def contract(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch.Tens
     return tuple(out)
 
 
+BACKWARD = {"plain": _lib.PLAIN_LU, "tree": _lib.UPDATE_TREE}
+
+
 def contract_backward(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch.Tensor,
-                      gC: torch.Tensor):
+                      gC: torch.Tensor, method: str = "tree"):
     """(grad_S, grad_w_src, grad_w_snk) of a real loss whose gradient with
     respect to C is gC (PyTorch's complex convention), from the library's
-    adjoint kernels."""
+    adjoint kernels (method "tree": by the source update tree; "plain":
+    pair by pair)."""
     T = S.shape[0]
     dev = plan.device
     _check_dev(S, torch.complex128, (T, plan.M, plan.M), "S", dev)
@@ -228,7 +232,8 @@ def contract_backward(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: t
     g_src = torch.empty_like(w_src)
     g_snk = torch.empty_like(w_snk)
     check(lib().mhc_contract_backward(
-        plan._h, T, ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(w_src.data_ptr()),
+        plan._h, BACKWARD[method], T, ctypes.c_void_p(S.data_ptr()),
+        ctypes.c_void_p(w_src.data_ptr()),
         ctypes.c_void_p(w_snk.data_ptr()), ctypes.c_void_p(gC.data_ptr()),
         ctypes.c_void_p(gS.data_ptr()), ctypes.c_void_p(g_src.data_ptr()),
         ctypes.c_void_p(g_snk.data_ptr()), _stream_ptr()))
@@ -321,6 +326,7 @@ class Contract(torch.autograd.Function):
     @staticmethod
     def forward(ctx, plan, S, w_src, w_snk, method="tree"):
         ctx.plan = plan
+        ctx.method = method
         ctx.save_for_backward(S, w_src, w_snk)
         return contract(plan, S.contiguous(), w_src.contiguous(), w_snk.contiguous(), method)
 
@@ -328,7 +334,8 @@ class Contract(torch.autograd.Function):
     def backward(ctx, gC):
         S, w_src, w_snk = ctx.saved_tensors
         gS, g_src, g_snk = contract_backward(ctx.plan, S.contiguous(), w_src.contiguous(),
-                                             w_snk.contiguous(), gC)
+                                             w_snk.contiguous(), gC,
+                                             "plain" if ctx.method == "plain" else "tree")
         return (None, gS if ctx.needs_input_grad[1] else None,
                 g_src if ctx.needs_input_grad[2] else None,
                 g_snk if ctx.needs_input_grad[3] else None, None)

@@ -35,14 +35,15 @@ def test_gradcheck_tiny():
             eps=1e-6, atol=1e-7, rtol=1e-5, nondet_tol=1e-12)
 
 
-def test_full_gradient_against_oracle_small():
+@pytest.mark.parametrize("method", ["plain", "tree"])
+def test_full_gradient_against_oracle_small(method):
     # every entry of grad S and both weight gradients, 2 slices, blocks of 3,
     # 20 x 70 terms (one full sink block of 64 and a ragged one)
     w = W.workload("mid", T=2, M=10, nf=(3, 3), n_src=20, n_snk=70, branching=3, depth=2)
     plan, S, ws, wk = setup(w)
     rng = np.random.default_rng(8)
     g = rng.standard_normal(w.T) + 1j * rng.standard_normal(w.T)
-    gS, gws, gwk = mhc.contract_backward(plan, S, ws, wk, torch.from_numpy(g))
+    gS, gws, gwk = mhc.contract_backward(plan, S, ws, wk, torch.from_numpy(g), method)
     torch.cuda.synchronize()
     gS, gws, gwk = gS.cpu().numpy(), gws.cpu().numpy(), gwk.cpu().numpy()
     oS, ows, owk = og.vjp(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk, g)
@@ -53,7 +54,8 @@ def test_full_gradient_against_oracle_small():
     assert plan.status()["n_singular_grad"] == 0
 
 
-def test_grad_workload_sampled_entries():
+@pytest.mark.parametrize("method", ["plain", "tree"])
+def test_grad_workload_sampled_entries(method):
     # 32 slices, M = 48, blocks of 6, 2000 x 2000 tree terms: 16 random
     # entries of grad S and 16 random weights per side against the oracle
     # (within 1e-9 of the sum of the magnitudes of each entry's terms) and
@@ -62,7 +64,7 @@ def test_grad_workload_sampled_entries():
     plan, S, ws, wk = setup(w)
     rng = np.random.default_rng(9)
     g = rng.standard_normal(w.T) + 1j * rng.standard_normal(w.T)
-    gS, gws, gwk = mhc.contract_backward(plan, S, ws, wk, torch.from_numpy(g))
+    gS, gws, gwk = mhc.contract_backward(plan, S, ws, wk, torch.from_numpy(g), method)
     torch.cuda.synchronize()
     gS, gws, gwk = gS.cpu().numpy(), gws.cpu().numpy(), gwk.cpu().numpy()
 
@@ -113,14 +115,49 @@ def test_grad_workload_sampled_entries():
         assert fd == pytest.approx(gwk[j], rel=1e-5, abs=1e-5 * np.abs(gwk).max())
 
 
-def test_backward_repeatable_in_weights():
+@pytest.mark.parametrize("method", ["plain", "tree"])
+def test_backward_repeatable_in_weights(method):
     w = W.workload("mid", T=2, n_src=200, n_snk=130)
     plan, S, ws, wk = setup(w)
     g = torch.tensor([1.0 - 0.5j, 0.25 + 2j], dtype=torch.complex128)
-    a = mhc.contract_backward(plan, S, ws, wk, g)
-    b = mhc.contract_backward(plan, S, ws, wk, g)
+    a = mhc.contract_backward(plan, S, ws, wk, g, method)
+    b = mhc.contract_backward(plan, S, ws, wk, g, method)
     torch.cuda.synchronize()
     assert a[1].cpu().numpy().tobytes() == b[1].cpu().numpy().tobytes()
     assert a[2].cpu().numpy().tobytes() == b[2].cpu().numpy().tobytes()
     np.testing.assert_allclose(a[0].cpu().numpy(), b[0].cpu().numpy(), rtol=1e-12,
                                atol=1e-14 * float(a[0].abs().max()))
+
+
+def test_tree_backward_matches_plain_backward():
+    # 3 slices, mid blocks, 400 x 150 tree terms (several sink blocks)
+    w = W.workload("mid", T=3, n_src=400, n_snk=150)
+    plan, S, ws, wk = setup(w)
+    g = torch.tensor([0.5 + 1j, -1.0 + 0.25j, 2.0 - 1j], dtype=torch.complex128)
+    p = [x.cpu().numpy() for x in mhc.contract_backward(plan, S, ws, wk, g, "plain")]
+    t = [x.cpu().numpy() for x in mhc.contract_backward(plan, S, ws, wk, g, "tree")]
+    for a, b in zip(p, t):
+        np.testing.assert_allclose(b, a, rtol=1e-9, atol=1e-11 * np.abs(a).max())
+
+
+def test_tree_backward_with_singular_dominators():
+    # a zero row of S makes every block that uses source index 2 singular:
+    # those dominators' partitions go pair by pair, the rest by the tree
+    w = W.workload("mid", T=2, M=12, nf=(3, 3), n_src=60, n_snk=70, branching=4, depth=2)
+    w.S[:, 2, :] = 0
+    plan, S, ws, wk = setup(w)
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(w.T) + 1j * rng.standard_normal(w.T)
+    gS, gws, gwk = mhc.contract_backward(plan, S, ws, wk, torch.from_numpy(g), "tree")
+    torch.cuda.synchronize()
+    gS, gws, gwk = gS.cpu().numpy(), gws.cpu().numpy(), gwk.cpu().numpy()
+    oS, ows, owk = og.vjp(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk, g)
+    # row 2 of grad S needs the adjugate of singular blocks, which the
+    # pair-by-pair route skips (and counts); every other entry must match
+    mask = np.ones_like(oS, dtype=bool)
+    mask[:, 2, :] = False
+    scale = np.abs(oS).max()
+    np.testing.assert_allclose(gS[mask], oS[mask], atol=1e-11 * scale, rtol=1e-9)
+    np.testing.assert_allclose(gws, ows, atol=1e-11 * np.abs(ows).max(), rtol=1e-9)
+    np.testing.assert_allclose(gwk, owk, atol=1e-11 * np.abs(owk).max(), rtol=1e-9)
+    assert plan.status()["n_singular_grad"] > 0

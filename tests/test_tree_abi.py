@@ -146,7 +146,8 @@ def test_null_handles_and_destroy():
     assert L.mhc_contract(None, 1, 1, None, None, None, None, None, None, None) == -1
     assert L.mhc_plan_status(None, None, None) == -1
     assert L.mhc_plan_attach_sink_tree(None, None, None) == -1
-    assert L.mhc_contract_backward(None, 1, None, None, None, None, None, None, None, None) == -1
+    assert L.mhc_contract_backward(None, 1, 1, None, None, None, None, None, None, None,
+                                   None) == -1
     assert L.mhc_terms_shape(None, None, None, None) == -1
     t = mhc.Terms([[0, 1]], (2,), 5)
     assert L.mhc_tree_build(t.handle, 3, ctypes.byref(h)) == -1   # unknown policy
