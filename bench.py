@@ -34,14 +34,14 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # sources they were measured on (SHA-256 below); null otherwise.
 TRAFFIC = {
     "workload": "mid",
-    "bytes": 6983.1 * 1.99973 * 1024 + 3680.0 * 1024,
+    "bytes": 6982.1 * 1.99973 * 1024 + 3680.0 * 1024,
     "sources": {
         "paper_1411_3691_amd/csrc/contract_kernels.hip":
-            "d324102ece8ab21ff1226426f439bdbcf391c5db88b99f07e69879bd8cac0301",
+            "62abf6ad5841dcaafb137f20e89e4d4e719368edfe8c237c980144f49a241f51",
         "paper_1411_3691_amd/csrc/lu_device.h":
-            "0b2dae7d61d15c7903d0337049dca0125cfcfd99ab685ae43a18a1592b846f9b",
+            "94fab73fa988a7c3b762221b08d0a4c168447f50c1c186d2ffc2543c6c86d845",
         "paper_1411_3691_amd/csrc/contract_kernels.h":
-            "6365fe718a93463d8269a50c9a3f4e2431c375b915bebca9ea7650efd5f63c84",
+            "aa4e4935663a0a6ef6629b23370c541bbabc276e542f6b8f76fc3214cd7e4283",
     },
 }
 
