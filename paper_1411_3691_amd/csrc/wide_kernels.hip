@@ -564,7 +564,9 @@ static hipError_t launch_batch_wide_n(const BatchArgs& b, bool tree, bool with_a
                 : launch_batch_wide_m<GROUP, NMAX, false, 0>(b, grid, lds, s);
 }
 
-int wide_bucket(int nmax) { return nmax <= 8 ? 8 : nmax <= 12 ? 12 : nmax <= 16 ? 16 : 24; }
+int wide_bucket(int nmax) {
+  return nmax <= 8 ? 8 : nmax <= 12 ? 12 : nmax <= 16 ? 16 : nmax <= 18 ? 18 : 24;
+}
 
 hipError_t launch_batch_wide(const BatchArgs& b, int nmax, bool tree, bool with_a, int grid,
                              size_t lds, hipStream_t s) {
@@ -575,6 +577,8 @@ hipError_t launch_batch_wide(const BatchArgs& b, int nmax, bool tree, bool with_
       return launch_batch_wide_n<16, 12>(b, tree, with_a, grid, lds, s);
     case 16:
       return launch_batch_wide_n<16, 16>(b, tree, with_a, grid, lds, s);
+    case 18:
+      return launch_batch_wide_n<32, 18>(b, tree, with_a, grid, lds, s);
     default:
       return launch_batch_wide_n<32, 24>(b, tree, with_a, grid, lds, s);
   }
@@ -589,6 +593,8 @@ hipError_t launch_contract_wide(const ContractArgs& a, int nmax, bool tree, bool
     e = launch_wide_n<16, 12>(a, tree, diag, s);
   else if (nmax <= 16)
     e = launch_wide_n<16, 16>(a, tree, diag, s);
+  else if (nmax <= 18)
+    e = launch_wide_n<32, 18>(a, tree, diag, s);
   else if (nmax <= 24)
     e = launch_wide_n<32, 24>(a, tree, diag, s);
   else
