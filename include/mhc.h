@@ -140,7 +140,8 @@ void mhc_tree_destroy(mhc_tree* tree);
  * Both term sets must have the same flavour structure and M.  Flavour blocks
  * may differ in size; the largest must be <= 24, and one slice of S as the
  * kernels keep it in LDS (rows padded to M + 1 entries, M * (M + 1) * 16
- * bytes) must fit in 150 KiB (M <= 97); otherwise MHC_E_UNSUPPORTED.  Enqueues the uploads on `stream` and waits for them. */
+ * bytes) must fit in 150 KiB (M <= 97); otherwise MHC_E_UNSUPPORTED.
+ * Enqueues the uploads on `stream` and waits for them. */
 mhc_status mhc_plan_create(const mhc_tree* src_tree, const mhc_terms* snk,
                            void* stream, mhc_plan** out);
 void mhc_plan_destroy(mhc_plan* plan);
@@ -155,9 +156,12 @@ void mhc_plan_destroy(mhc_plan* plan);
  *   pair_det  complex128 [T][n_src][n_snk] or NULL: every d_ij(t) =
  *             prod_f det G_f^(ij)(t) (output; a test hook, at most 4
  *             flavour blocks)
- * T >= 1.  method is MHC_PLAIN_LU or MHC_UPDATE_TREE; both return the same
- * quantities within floating-point rounding.  Every pointer must stay valid
- * until the stream has run the work. */
+ * T in [1, 65535].  Every method returns the same quantities within
+ * floating-point rounding: MHC_PLAIN_LU, MHC_UPDATE_TREE (the paper's
+ * method), MHC_UPDATE_TREE2 (needs an attached sink tree, computes neither
+ * A nor pair_det: both must be NULL) and the unpivoted ablations (blocks of
+ * one size n <= 8).  Every pointer must stay valid until the stream has run
+ * the work. */
 mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
                         const void* S, const double* w_src,
                         const double* w_snk, void* C, double* A,
@@ -191,9 +195,10 @@ mhc_status mhc_contract_backward(mhc_plan* plan, int32_t method, int32_t T, cons
 
 /* Counters summed over all completed calls on this plan (either pointer may
  * be NULL); synchronises the device first.
- *   n_fallback       children whose flavour block the update path took by
- *                    direct LU because the dominator block had an exactly
- *                    zero pivot (no inverse);
+ *   n_fallback       work the update paths took by direct LU because a
+ *                    dominator block had an exactly zero pivot (no
+ *                    inverse): children (MHC_UPDATE_TREE), or (source
+ *                    dominator, sink dominator) pairs (MHC_UPDATE_TREE2);
  *   n_singular_grad  (pair, flavour) blocks with an exactly zero pivot that
  *                    the adjoint skipped. */
 mhc_status mhc_plan_status(mhc_plan* plan, int64_t* n_fallback,

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
-    assert L.mhc_version() >= 100
+    assert L.mhc_version() >= 200
 
 
 def tree_matches_oracle(terms, nf, M, policy):
