@@ -161,7 +161,10 @@ void mhc_plan_destroy(mhc_plan* plan);
  * method), MHC_UPDATE_TREE2 (needs an attached sink tree, computes neither
  * A nor pair_det: both must be NULL) and the unpivoted ablations (blocks of
  * one size n <= 8).  Every pointer must stay valid until the stream has run
- * the work. */
+ * the work.  The plan holds the workgroup partial sums: two contractions on
+ * one plan that overlap in time (on different streams) race; a call that
+ * needs a larger partial buffer than any before waits for the device, then
+ * grows it. */
 mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
                         const void* S, const double* w_src,
                         const double* w_snk, void* C, double* A,

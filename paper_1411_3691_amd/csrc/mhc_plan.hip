@@ -357,7 +357,8 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   const size_t need = (size_t)T * n_blk_t * 3;
   if (need > pl->partial_cap) {
     if (pl->partial) {
-      e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+      // earlier calls may still read the old buffer, on any stream
+      e = hipDeviceSynchronize();
       if (e != hipSuccess) return hip_fail(e, "mhc_contract/sync");
       hipFree(pl->partial);
       pl->partial = nullptr;
@@ -430,7 +431,8 @@ mhc_status mhc_contract_backward(mhc_plan* pl, int32_t method, int32_t T, const 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (need > pl->adj_cap) {
     if (pl->adj_scratch) {
-      e = hipStreamSynchronize(s);
+      // earlier calls may still use the old scratch, on any stream
+      e = hipDeviceSynchronize();
       if (e != hipSuccess) return hip_fail(e, "mhc_contract_backward/sync");
       hipFree(pl->adj_scratch);
       pl->adj_scratch = nullptr;
