@@ -341,17 +341,25 @@ def main():
 
     wall_tree, ev_tree, C_tree = timed("tree")
     wall_plain, ev_plain, C_plain = timed("plain")
+    fl_tree = tree_flops(w.T, len(w.snk), w.nf, tree.export())
     abl = None
     if args.workload == "mid":
         # the paper's variants (Sec. 4, Fig. 1 caption) on the same inputs:
-        # LU without pivoting, and updates without shared solves
+        # LU without pivoting, and updates without shared solves; and LU
+        # with threshold partial pivoting
         abl = {}
         for name, method in (("plain_unpivoted", "plain_unpivoted"),
-                             ("tree_unpivoted", "tree_unpivoted")):
+                             ("tree_unpivoted", "tree_unpivoted"),
+                             ("plain_threshold_pivoting", "plain_threshold"),
+                             ("tree_threshold_pivoting", "tree_threshold")):
             wall_a, ev_a, _ = timed(method)
             abl[name] = {"ms_per_step": wall_a * 1e3 / args.steps,
                          "kernel_ms": float(np.mean(ev_a)),
                          "value": w.n_pairs / (wall_a / args.steps)}
+            if method == "tree_threshold":
+                a_t = fl_tree / (float(np.mean(ev_a)) * 1e-3) / 1e12
+                abl[name]["tflops"] = a_t
+                abl[name]["frac"] = a_t / FP64_PEAK_TFLOPS
         tree_ns = mhc.Tree(src, share=False)
         plan_ns = mhc.Plan(tree_ns, snk)
         plan_main = plan
@@ -407,7 +415,6 @@ def main():
     ms_plain = wall_plain * 1e3 / args.steps
     ev_tree_ms = float(np.mean(ev_tree))
     ev_plain_ms = float(np.mean(ev_plain))
-    fl_tree = tree_flops(w.T, len(w.snk), w.nf, tree.export())
     fl_plain = plain_flops(w.T, len(w.src), len(w.snk), w.nf)
     ach = fl_tree / (ev_tree_ms * 1e-3) / 1e12
     rel = float(np.max(np.abs(C_tree - C_plain)) / max(1e-300, float(np.max(np.abs(C_plain)))))

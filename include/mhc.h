@@ -77,7 +77,13 @@ enum {
    * pivoting): the same two methods with the diagonal as every pivot.  Not
    * backward stable; every block must have one size n <= 8. */
   MHC_PLAIN_LU_UNPIVOTED = 3,
-  MHC_UPDATE_TREE_UNPIVOTED = 4
+  MHC_UPDATE_TREE_UNPIVOTED = 4,
+  /* Variants with threshold partial pivoting: the diagonal entry stays the
+   * pivot unless it is below 0.1 times the column's largest |Re|+|Im|
+   * (growth per step at most 11), so rows rarely move.  Every block must
+   * have one size n <= 8. */
+  MHC_PLAIN_LU_THRESHOLD = 5,
+  MHC_UPDATE_TREE_THRESHOLD = 6
 };
 
 typedef struct mhc_terms mhc_terms;
@@ -159,8 +165,8 @@ void mhc_plan_destroy(mhc_plan* plan);
  * T in [1, 65535].  Every method returns the same quantities within
  * floating-point rounding: MHC_PLAIN_LU, MHC_UPDATE_TREE (the paper's
  * method), MHC_UPDATE_TREE2 (needs an attached sink tree, computes neither
- * A nor pair_det: both must be NULL) and the unpivoted ablations (blocks of
- * one size n <= 8).  Every pointer must stay valid until the stream has run
+ * A nor pair_det: both must be NULL), the unpivoted ablations and the
+ * threshold-pivoting variants (blocks of one size n <= 8).  Every pointer must stay valid until the stream has run
  * the work.  The plan holds the workgroup partial sums: two contractions on
  * one plan that overlap in time (on different streams) race; a call that
  * needs a larger partial buffer than any before waits for the device, then

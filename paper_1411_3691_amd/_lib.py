@@ -27,6 +27,8 @@ UPDATE_TREE = 1
 UPDATE_TREE2 = 2
 PLAIN_LU_UNPIVOTED = 3
 UPDATE_TREE_UNPIVOTED = 4
+PLAIN_LU_THRESHOLD = 5
+UPDATE_TREE_THRESHOLD = 6
 TREE_NO_SHARING = 0x100
 SCHED_AUTO = 0
 SCHED_LANE = 1

@@ -70,7 +70,8 @@ constexpr int kPairFlavors = 4;
 // flavour block of size n <= 8) and the final reduction into C[T] (and A[T]
 // if non-null).  diag selects the kernels that also produce A and pair
 // determinants.  Work items are (row set, block of 64 sinks).
-hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag, bool pivot,
+// pivot: 0 none (ablation), 1 partial pivoting, 2 threshold partial pivoting.
+hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag, int pivot,
                            double2* C, double* A, hipStream_t s);
 
 // The same with one group of lanes per matrix (one row per lane): blocks of

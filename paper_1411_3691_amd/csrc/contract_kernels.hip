@@ -61,7 +61,7 @@ __device__ __forceinline__ void child_det_direct(const char* lds,
 }
 
 // MODE bit 0: accumulate A(t) = sum |w w d|; bit 1: write every pair det;
-// bit 2: no pivoting (ablation).
+// bit 2: no pivoting (ablation); bit 3: threshold partial pivoting.
 // One tile: slice t, the chunk-th strided share of the slice's work items.
 // The workgroup stages S_t in LDS (smem), walks its items and writes one
 // partial (re, im, A) for (t, chunk).
@@ -70,6 +70,7 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
                                           double2* smem) {
   constexpr bool WITH_A = (MODE & 1) != 0;
   constexpr bool PIVOT = (MODE & 4) == 0;
+  constexpr bool THRESH = (MODE & 8) != 0;
   constexpr bool WITH_PAIRS = (MODE & 2) != 0;
   const PlanView& p = a.plan;
   __syncthreads();  // the previous tile of this workgroup is done with LDS
@@ -133,7 +134,7 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
           int perm[N];
           bool z;
           gather<N>(lds, ro, co, gr, gi);
-          lu<N, TREE, PIVOT>(gr, gi, Dpre_re[f], Dpre_im[f], perm, z);
+          lu<N, TREE, PIVOT, THRESH>(gr, gi, Dpre_re[f], Dpre_im[f], perm, z);
         }
       }
     }
@@ -161,7 +162,7 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
       // The tree keeps the multipliers for every dominator block: nearly
       // every dominator has groups in every flavour, and a single
       // factorisation path keeps the register allocation within budget.
-      lu<N, TREE, PIVOT>(gr, gi, dre, dim, perm, zero);
+      lu<N, TREE, PIVOT, THRESH>(gr, gi, dre, dim, perm, zero);
       if (TREE) {
         double sre = 0.0, sim = 0.0;
         for (int gg = g; gg < g_f_end; ++gg) {
@@ -371,8 +372,12 @@ static hipError_t launch_one(const ContractArgs& a, hipStream_t s) {
 }
 
 template <int N>
-static hipError_t launch_n(const ContractArgs& a, bool tree, bool diag, bool pivot,
+static hipError_t launch_n(const ContractArgs& a, bool tree, bool diag, int pivot,
                            hipStream_t s) {
+  if (pivot == 2) {
+    if (tree) return diag ? launch_one<N, true, 11>(a, s) : launch_one<N, true, 8>(a, s);
+    return diag ? launch_one<N, false, 11>(a, s) : launch_one<N, false, 8>(a, s);
+  }
   if (!pivot) {
     if (tree) return diag ? launch_one<N, true, 7>(a, s) : launch_one<N, true, 4>(a, s);
     return diag ? launch_one<N, false, 7>(a, s) : launch_one<N, false, 4>(a, s);
@@ -381,7 +386,7 @@ static hipError_t launch_n(const ContractArgs& a, bool tree, bool diag, bool piv
   return diag ? launch_one<N, false, 3>(a, s) : launch_one<N, false, 0>(a, s);
 }
 
-hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag, bool pivot,
+hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag, int pivot,
                            double2* C, double* A, hipStream_t s) {
   hipError_t e;
   switch (n) {

@@ -150,7 +150,13 @@ __device__ __forceinline__ double pivot_key(double re, double im, int m) {
 // exactly zero.
 // PIVOT = false (an ablation of the paper's unpivoted 6x6 LU, Sec. 4):
 // the pivot of step k is the diagonal entry, no rows are exchanged.
-template <int N, bool KEEP, bool PIVOT = true>
+// THRESH = true (threshold partial pivoting, a variant): the diagonal entry
+// stays the pivot unless it is below kThreshold times the column's largest
+// |Re|+|Im|; the growth per step is then at most 1 + 1/kThreshold, and rows
+// move only where a lane needs it (a step no lane pivots in is skipped).
+constexpr double kThreshold = 0.1;
+
+template <int N, bool KEEP, bool PIVOT = true, bool THRESH = false>
 __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
                                    double& dre, double& dim, int (&perm)[N],
                                    bool& zero_pivot) {
@@ -168,11 +174,15 @@ __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
     double key = pivot_key(gr[k][k], gi[k][k], k);
 #pragma unroll
     for (int m = k + 1; m < N; ++m) key = fmax(key, pivot_key(gr[m][k], gi[m][k], m));
-    const int p = 7 - (int)(__double2loint(key) & 7u);
+    int p = 7 - (int)(__double2loint(key) & 7u);
+    if (THRESH) {
+      const double dmag = fabs(gr[k][k]) + fabs(gi[k][k]);
+      if (dmag >= kThreshold * key) p = k;
+    }
     // Row exchange k <-> p: row k's old value is saved, then for each
     // candidate row m the lanes that chose m move row m into row k and the
     // saved row into row m (the L part too when the factors are kept).
-    if (k + 1 < N) {
+    if (k + 1 < N && (!THRESH || __builtin_amdgcn_ballot_w64(p != k) != 0)) {
       const int jb = KEEP ? 0 : k;
       double tr[N], ti[N];
       int tp = 0;
@@ -185,6 +195,7 @@ __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
 #pragma unroll
       for (int m = k + 1; m < N; ++m) {
         const uint64_t mask = __builtin_amdgcn_ballot_w64(p == m);
+        if (THRESH && mask == 0) continue;
 #pragma unroll
         for (int j = jb; j < N; j += 3) {
           if (j + 2 < N) {

@@ -314,13 +314,16 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
     return fail(MHC_E_ARG, "mhc_contract: NULL buffer");
   if (T < 1) return fail(MHC_E_ARG, "mhc_contract: T < 1");
   if (T > 65535) return fail(MHC_E_ARG, "mhc_contract: T > 65535");
-  if (method != MHC_PLAIN_LU && method != MHC_UPDATE_TREE && method != MHC_UPDATE_TREE2 &&
-      method != MHC_PLAIN_LU_UNPIVOTED && method != MHC_UPDATE_TREE_UNPIVOTED)
+  if (method < MHC_PLAIN_LU || method > MHC_UPDATE_TREE_THRESHOLD)
     return fail(MHC_E_ARG, "mhc_contract: unknown method");
-  const bool pivot = method != MHC_PLAIN_LU_UNPIVOTED && method != MHC_UPDATE_TREE_UNPIVOTED;
-  if (!pivot && !(pl->uniform_n && pl->n <= 8))
+  const int pivot = (method == MHC_PLAIN_LU_UNPIVOTED || method == MHC_UPDATE_TREE_UNPIVOTED) ? 0
+                    : (method == MHC_PLAIN_LU_THRESHOLD || method == MHC_UPDATE_TREE_THRESHOLD)
+                        ? 2
+                        : 1;
+  if (pivot != 1 && !(pl->uniform_n && pl->n <= 8))
     return fail(MHC_E_UNSUPPORTED,
-                "mhc_contract: the unpivoted methods need every flavour block of size n <= 8");
+                "mhc_contract: the unpivoted and threshold-pivoting methods need every flavour "
+                "block of size n <= 8");
   if (method == MHC_UPDATE_TREE2) {
     if (!pl->dev_tree2)
       return fail(MHC_E_STATE, "mhc_contract: no sink tree attached to the plan");
@@ -338,7 +341,8 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_contract: pair_det output supports at most 4 flavour blocks");
   const bool two = method == MHC_UPDATE_TREE2;
-  const bool tree = method == MHC_UPDATE_TREE || method == MHC_UPDATE_TREE_UNPIVOTED;
+  const bool tree = method == MHC_UPDATE_TREE || method == MHC_UPDATE_TREE_UNPIVOTED ||
+                    method == MHC_UPDATE_TREE_THRESHOLD;
   const bool diag = A != nullptr || pair_det != nullptr;
   // one matrix per lane when every block has the same size n <= 8, else one
   // group of lanes per matrix

@@ -23,7 +23,10 @@ from ._lib import check, lib
 METHODS = {"plain": _lib.PLAIN_LU, "tree": _lib.UPDATE_TREE, "tree2": _lib.UPDATE_TREE2,
            # ablations: no pivoting (blocks of one size n <= 8)
            "plain_unpivoted": _lib.PLAIN_LU_UNPIVOTED,
-           "tree_unpivoted": _lib.UPDATE_TREE_UNPIVOTED}
+           "tree_unpivoted": _lib.UPDATE_TREE_UNPIVOTED,
+           # threshold partial pivoting (blocks of one size n <= 8)
+           "plain_threshold": _lib.PLAIN_LU_THRESHOLD,
+           "tree_threshold": _lib.UPDATE_TREE_THRESHOLD}
 POLICIES = {"R1": _lib.GREEDY_R1, "R2": _lib.GREEDY_R2}
 
 

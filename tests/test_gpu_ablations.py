@@ -56,3 +56,35 @@ def test_unpivoted_lu_refuses_uneven_blocks():
     plan, tree, S, ws, wk = upload(w)
     with pytest.raises(MhcError, match="MHC_E_UNSUPPORTED"):
         mhc.contract(plan, S, ws, wk, "plain_unpivoted")
+
+
+def run_pairs(plan, S, ws, wk, method):
+    C, A, P = mhc.contract(plan, S, ws, wk, method, with_scale=True, with_pairs=True)
+    torch.cuda.synchronize()
+    return C.cpu().numpy(), A.cpu().numpy(), P.cpu().numpy()
+
+
+@pytest.mark.parametrize("method", ["plain_threshold", "tree_threshold"])
+def test_threshold_pivoting_every_pair(method):
+    # threshold partial pivoting must meet the same per-pair tolerance as
+    # partial pivoting (3 slices, 300 x 200 tree terms: every pair)
+    from parity_util import all_pairs, check_C, check_pairs
+    w = W.workload("mid", T=3, n_src=300, n_snk=200)
+    plan, tree, S, ws, wk = upload(w)
+    C, A, P = run_pairs(plan, S, ws, wk, method)
+    check_pairs(w, P, *all_pairs(w))
+    Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+    check_C(C, A, Cw, Aw)
+
+
+@pytest.mark.parametrize("method", ["plain_threshold", "tree_threshold"])
+def test_threshold_pivoting_near_singular(method):
+    # two equal rows of S (blocks holding both are singular up to rounding)
+    from parity_util import all_pairs, check_C, check_pairs
+    w = W.workload("mid", T=2, M=12, n_src=300, n_snk=100, branching=6, depth=3)
+    w.S[:, 5, :] = w.S[:, 3, :]
+    plan, tree, S, ws, wk = upload(w)
+    C, A, P = run_pairs(plan, S, ws, wk, method)
+    check_pairs(w, P, *all_pairs(w))
+    Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+    check_C(C, A, Cw, Aw)
