@@ -30,18 +30,18 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # HBM bytes per launch of the update-tree kernel on the mid workload, from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script
 # (--copy-probe), each scaled by the same counter's reading for a 256 MiB
-# device copy (fetch x 1.9997, write x 1.0).  Valid only for the kernel
+# device copy (fetch x 1.99972, write x 1.0).  Valid only for the kernel
 # sources they were measured on (SHA-256 below); null otherwise.
 TRAFFIC = {
     "workload": "mid",
-    "bytes": 6982.1 * 1.99973 * 1024 + 3680.0 * 1024,
+    "bytes": 6976.8 * 1.99972 * 1024 + 3680.0 * 1024,
     "sources": {
         "paper_1411_3691_amd/csrc/contract_kernels.hip":
-            "62abf6ad5841dcaafb137f20e89e4d4e719368edfe8c237c980144f49a241f51",
+            "8ab4fe026738f4bd80b4f33d4e042f89c6ec1dd742d7271cb8752d3c18184c6c",
         "paper_1411_3691_amd/csrc/lu_device.h":
-            "94fab73fa988a7c3b762221b08d0a4c168447f50c1c186d2ffc2543c6c86d845",
+            "daa5cb09804b557f4ee977a026f6b7e80aef94617351bf0b7b09b91b013d109c",
         "paper_1411_3691_amd/csrc/contract_kernels.h":
-            "aa4e4935663a0a6ef6629b23370c541bbabc276e542f6b8f76fc3214cd7e4283",
+            "bc0486545e82593f3f41324d36fe1545d163913d26540dbc00a6858f71a8445b",
     },
 }
 
