@@ -26,20 +26,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
+SETTLE_S = 0.3              # untimed work before the first timed method
 
 # HBM bytes per launch of the update-tree kernel on the mid workload, from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script
 # (--copy-probe), each scaled by the same counter's reading for a 256 MiB
-# device copy (fetch x 1.99972, write x 1.0).  Valid only for the kernel
+# device copy (fetch x 1.99973, write x 1.0).  Valid only for the kernel
 # sources they were measured on (SHA-256 below); null otherwise.
 TRAFFIC = {
     "workload": "mid",
-    "bytes": 6976.8 * 1.99972 * 1024 + 3680.0 * 1024,
+    "bytes": 5725.2 * 1.99973 * 1024 + 1120.0 * 1024,
     "sources": {
         "paper_1411_3691_amd/csrc/contract_kernels.hip":
-            "8ab4fe026738f4bd80b4f33d4e042f89c6ec1dd742d7271cb8752d3c18184c6c",
+            "bc5b26980bb6a08384bb44f99a7fc3c6966a9b701933bdce6a5c5a429effaf9f",
         "paper_1411_3691_amd/csrc/lu_device.h":
-            "daa5cb09804b557f4ee977a026f6b7e80aef94617351bf0b7b09b91b013d109c",
+            "f9244cc21145d9d84294f81c1218d1d79b6b5c7743f2c8a5a003337207fc11ac",
         "paper_1411_3691_amd/csrc/contract_kernels.h":
             "bc0486545e82593f3f41324d36fe1545d163913d26540dbc00a6858f71a8445b",
     },
@@ -77,17 +78,32 @@ def f_ratio(n: int) -> int:
     return 8 * n + 12 + 5
 
 
-def tree_flops(T, n_snk, nf, tree) -> float:
+def f_solve_executed(n: int, r: int) -> int:
+    """Flops the narrow kernels execute for x = G^-1 e_r: with column
+    pivoting the unit vector stays at row r, so the forward part has
+    (n-r-1)(n-r-2)/2 complex MACs; the backward part n(n-1)/2 MACs, r of them
+    plain complex multiplies (rows above r start from zero), and n complex
+    multiplies by 1/U_mm.  f_solve (the paper's n^2 - n MACs) counts the
+    forward part in full."""
+    return 8 * ((n - r - 1) * (n - r - 2) // 2 + n * (n - 1) // 2) - 2 * r + 6 * n
+
+
+def tree_flops(T, n_snk, nf, tree, executed: bool = False) -> float:
     """Per (slice, sink): every dominator's blocks factorised (and the
     weighted product), one solve per (dominator, flavour, changed row) group
     and one ratio per child, each at its own flavour's block size; ``tree``
-    is the exported tree (owner, flavour and row of every term)."""
+    is the exported tree (owner, flavour and row of every term).  With
+    ``executed`` the solves are counted as the kernels execute them
+    (f_solve_executed) instead of by the convention (f_solve)."""
     import numpy as np
     owner, flav, pos = tree["owner"], tree["flav"], tree["pos"]
     child = owner != np.arange(len(owner))
     per_sink = tree["n_dom"] * float(sum(f_lu(n) for n in nf) + 11)
     groups = set(zip(owner[child].tolist(), flav[child].tolist(), pos[child].tolist()))
-    per_sink += sum(f_solve(nf[f]) for _, f, _ in groups)
+    if executed:
+        per_sink += sum(f_solve_executed(nf[f], r) for _, f, r in groups)
+    else:
+        per_sink += sum(f_solve(nf[f]) for _, f, _ in groups)
     per_sink += sum(f_ratio(nf[f]) for f in flav[child].tolist())
     return float(T) * n_snk * per_sink
 
@@ -323,6 +339,15 @@ def main():
         del a_, b_
     torch.cuda.synchronize()
 
+    # The GPU raises its clocks over the first tens of milliseconds of
+    # sustained work (back-to-back launches of one kernel run about 10 %
+    # faster after ~50 ms): run the update tree untimed for SETTLE_S seconds
+    # before the first timed method, then W warm-up steps per method.
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < SETTLE_S:
+        mhc.contract_into(plan, S, ws, wk, C, "tree")
+        torch.cuda.synchronize()
+
     def timed(method):
         for _ in range(args.warmup):
             mhc.contract_into(plan, S, ws, wk, C, method)
@@ -342,6 +367,11 @@ def main():
     wall_tree, ev_tree, C_tree = timed("tree")
     wall_plain, ev_plain, C_plain = timed("plain")
     fl_tree = tree_flops(w.T, len(w.snk), w.nf, tree.export())
+    # blocks of at most 8 take the lane-per-matrix kernels, whose solves
+    # skip the zero head of e_r
+    narrow = max(w.nf) <= 8
+    fl_tree_exec = (tree_flops(w.T, len(w.snk), w.nf, tree.export(), executed=True)
+                    if narrow else None)
     abl = None
     if args.workload == "mid":
         # the paper's variants (Sec. 4, Fig. 1 caption) on the same inputs:
@@ -446,7 +476,10 @@ def main():
         "speedup_vs_plain": (wall_plain / wall_tree),
         "tree_vs_plain_max_rel_diff": rel,
         "tree": {**st, "rho": st["n_dom"] / st["n_terms"], "build_s": t_tree,
-                 "kernel_ms": ev_tree_ms, "flops_per_step": fl_tree},
+                 "kernel_ms": ev_tree_ms, "flops_per_step": fl_tree,
+                 "flops_executed_per_step": fl_tree_exec,
+                 "frac_executed": (fl_tree_exec / (ev_tree_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
+                                   if narrow else None)},
         "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(args.workload)},

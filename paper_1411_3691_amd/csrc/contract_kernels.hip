@@ -11,14 +11,18 @@
 // entries from LDS.
 //
 //  * plain method (Sec. 2, LU route): the row set is one source term;
-//    per flavour block: gather G_f, GEPP, det; d = prod_f det_f.
+//    per flavour block: LU with partial pivoting, gathering G_f from LDS as
+//    the factorisation proceeds (Crout order, column exchanges), det;
+//    d = prod_f det_f.
 //  * update tree (Secs. 2-3): the row set is a dominator.  Per flavour
-//    block: gather, GEPP keeping L, U and the row permutation; for every
+//    block: the same LU keeping L, U and the column order; for every
 //    group (f, r) of the dominator one solve x = G_f^-1 e_r (forward and
-//    back substitution); every child of the group then costs one dot
-//    product: det(G with row r := s) = det(G) * (s . x) (matrix determinant
-//    lemma, Sec. 2; s . x equals 1 + v^T G^-1 e_r with v = s - old row).
-//    Children with the same (f, r) share x (the "caching" of Sec. 2).
+//    back substitution; with column pivoting e_r is not permuted, so the
+//    forward part starts at row r); every child of the group then costs
+//    one dot product: det(G with row r := s) = det(G) * (s . x) (matrix
+//    determinant lemma, Sec. 2; s . x equals 1 + v^T G^-1 e_r with
+//    v = s - old row).  Children with the same (f, r) share x (the
+//    "caching" of Sec. 2).
 //
 // The weighted sum over one item folds the flavours incrementally: with
 // P = prod of the dets seen so far and Q = sum over seen flavours f of
@@ -69,8 +73,7 @@ template <int N, bool TREE, int MODE>
 __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chunk,
                                           double2* smem) {
   constexpr bool WITH_A = (MODE & 1) != 0;
-  constexpr bool PIVOT = (MODE & 4) == 0;
-  constexpr bool THRESH = (MODE & 8) != 0;
+  constexpr int PIV = (MODE & 4) ? kNoPivot : (MODE & 8) ? kThresholdPivot : kPartialPivot;
   constexpr bool WITH_PAIRS = (MODE & 2) != 0;
   const PlanView& p = a.plan;
   __syncthreads();  // the previous tile of this workgroup is done with LDS
@@ -131,10 +134,8 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
             co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + k];
           }
           double gr[N][N], gi[N][N];
-          int perm[N];
           bool z;
-          gather<N>(lds, ro, co, gr, gi);
-          lu<N, TREE, PIVOT, THRESH>(gr, gi, Dpre_re[f], Dpre_im[f], perm, z);
+          lu_crout<N, TREE, PIV>(lds, ro, co, gr, gi, Dpre_re[f], Dpre_im[f], z);
         }
       }
     }
@@ -149,7 +150,6 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
         co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + k];
       }
       double gr[N][N], gi[N][N];
-      int perm[N];
       double dre, dim;
       bool zero;
       // groups of this flavour form a contiguous run [g, g_f_end)
@@ -158,45 +158,46 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
         while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
       }
       double accre = 0.0, accim = 0.0;
-      gather<N>(lds, ro, co, gr, gi);
       // The tree keeps the multipliers for every dominator block: nearly
       // every dominator has groups in every flavour, and a single
       // factorisation path keeps the register allocation within budget.
-      lu<N, TREE, PIVOT, THRESH>(gr, gi, dre, dim, perm, zero);
+      // The factorisation leaves co in its column order, which is the
+      // order of the solved vectors x below.
+      lu_crout<N, TREE, PIV>(lds, ro, co, gr, gi, dre, dim, zero);
       if (TREE) {
         double sre = 0.0, sim = 0.0;
         for (int gg = g; gg < g_f_end; ++gg) {
           const int r = uniform(p.grp_fr[gg] & 0xff);
-          double xr[N], xi[N];
-          solve_unit<N>(gr, gi, perm, r, xr, xi);
           const int c_begin = uniform(p.grp_ptr[gg]);
           const int c_end = uniform(p.grp_ptr[gg + 1]);
-          for (int c = c_begin; c < c_end; ++c) {
-            const uint32_t crow = uniform(p.child_rowoff[c]);
-            const int cterm = uniform(p.child_term[c]);
-            double rr = 0.0, ri = 0.0;
+          solve_unit_col<N>(gr, gi, r, gg, [&](const double (&xr)[N], const double (&xi)[N]) {
+            for (int c = c_begin; c < c_end; ++c) {
+              const uint32_t crow = uniform(p.child_rowoff[c]);
+              const int cterm = uniform(p.child_term[c]);
+              double rr = 0.0, ri = 0.0;
 #pragma unroll
-            for (int n = 0; n < N; ++n) {
-              const double2 s = *reinterpret_cast<const double2*>(lds + crow + co[n]);
-              rr = rr + s.x * xr[n] - s.y * xi[n];
-              ri = ri + s.x * xi[n] + s.y * xr[n];
-            }
-            const double wc = a.w_src[cterm];
-            sre += wc * rr;
-            sim += wc * ri;
-            if (WITH_A && !zero) sabs_reg += fabs(wc) * sqrt(rr * rr + ri * ri);
-            if (WITH_PAIRS && valid && a.pair_det && !zero) {
-              double cr = rr * dre - ri * dim, ci = rr * dim + ri * dre;
-#pragma unroll
-              for (int q = 0; q < kPairFlavors; ++q) {
-                if (q == f || q >= F) continue;
-                const double tr = cr * Dpre_re[q] - ci * Dpre_im[q];
-                ci = cr * Dpre_im[q] + ci * Dpre_re[q];
-                cr = tr;
+              for (int n = 0; n < N; ++n) {
+                const double2 s = *reinterpret_cast<const double2*>(lds + crow + co[n]);
+                rr = rr + s.x * xr[n] - s.y * xi[n];
+                ri = ri + s.x * xi[n] + s.y * xr[n];
               }
-              a.pair_det[((size_t)t * p.n_src + cterm) * p.n_snk + k] = make_double2(cr, ci);
+              const double wc = a.w_src[cterm];
+              sre += wc * rr;
+              sim += wc * ri;
+              if (WITH_A && !zero) sabs_reg += fabs(wc) * sqrt(rr * rr + ri * ri);
+              if (WITH_PAIRS && valid && a.pair_det && !zero) {
+                double cr = rr * dre - ri * dim, ci = rr * dim + ri * dre;
+#pragma unroll
+                for (int q = 0; q < kPairFlavors; ++q) {
+                  if (q == f || q >= F) continue;
+                  const double tr = cr * Dpre_re[q] - ci * Dpre_im[q];
+                  ci = cr * Dpre_im[q] + ci * Dpre_re[q];
+                  cr = tr;
+                }
+                a.pair_det[((size_t)t * p.n_src + cterm) * p.n_snk + k] = make_double2(cr, ci);
+              }
             }
-          }
+          });
         }
         // acc_f = det_f * sum_c w_c ratio_c  (0 for a zero-pivot block)
         accre = zero ? 0.0 : dre * sre - dim * sim;

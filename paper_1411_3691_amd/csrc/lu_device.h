@@ -328,6 +328,239 @@ __device__ __forceinline__ void solve_row(const double (&gr)[N][N], const double
   }
 }
 
+__device__ __forceinline__ void masked_exchange_u32(uint64_t mask, uint32_t& a, uint32_t& b,
+                                                   uint32_t& t) {
+  uint64_t sv;
+  asm("s_and_saveexec_b64 %[sv], %[mask]\n\t"
+      "v_mov_b32 %[a], %[b]\n\t"
+      "v_mov_b32 %[b], %[t]\n\t"
+      "s_mov_b64 exec, %[sv]"
+      : [a] "+v"(a), [b] "+v"(b), [t] "+v"(t), [sv] "=&s"(sv)
+      : [mask] "s"(mask)
+      : "scc");
+}
+
+// Pivot rule of lu_crout.
+enum PivotRule { kNoPivot = 0, kPartialPivot = 1, kThresholdPivot = 2 };
+
+// LU of the block G[m][n] = S_t[row m][col n] in Crout order with column
+// pivoting, gathering G from LDS as the factorisation needs it (rowoff,
+// coloff: byte offsets as for gather).  Step k forms row k of U (columns
+// k..N-1) from the original row k, read in the current column order, minus
+// its products with the finished rows 0..k-1 of U; the pivot is that row's
+// largest |Re| + |Im| (lowest column on ties); then column k of L is formed
+// from the original column k, read in the new order.  Because the rows
+// below k are still in LDS, a column exchange moves only rows 0..k and the
+// column offset: k + 1 complex entries instead of the N of a row exchange
+// in right-looking elimination, and no permutation vector is kept.
+// On return coloff holds the column order of the factors (G Q = L U, Q the
+// exchange of the original columns into that order); the strict lower
+// triangle holds L (unit diagonal), the upper triangle U, and with KEEP
+// the diagonal holds 1/U_mm.  det = sgn(Q) prod U_mm; zero_pivot reports an
+// exactly zero pivot (the row it occurs in is then zero from column k on).
+// kThresholdPivot keeps the diagonal candidate unless it is below
+// kThreshold times the row's largest entry and skips the exchange when no
+// lane of the wave needs it.  kNoPivot reads the whole block first and
+// eliminates right-looking (no exchanges, so nothing is gained by reading
+// late), leaving coloff and the factor layout as above.
+template <int N, bool KEEP, int PIV>
+__device__ __forceinline__ void lu_crout(const char* lds, const uint32_t (&rowoff)[N],
+                                         uint32_t (&coloff)[N], double (&gr)[N][N],
+                                         double (&gi)[N][N], double& dre, double& dim,
+                                         bool& zero_pivot) {
+  static_assert(N <= 8, "column rank is packed into 3 bits");
+  if constexpr (PIV == kNoPivot) {
+    int perm[N];
+    gather<N>(lds, rowoff, coloff, gr, gi);
+    lu<N, KEEP, false>(gr, gi, dre, dim, perm, zero_pivot);
+    return;
+  }
+  double sre = 1.0, sim = 0.0;
+  bool neg = false;
+  zero_pivot = false;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    // Row k of U: u_j = G[k][j] - sum_{i<k} L[k][i] U[i][j], j >= k.
+#pragma unroll
+    for (int j = k; j < N; ++j) {
+      const double2 v = *reinterpret_cast<const double2*>(lds + rowoff[k] + coloff[j]);
+      double ur = v.x, ui = v.y;
+#pragma unroll
+      for (int i = 0; i < k; ++i) {
+        ur = ur - gr[k][i] * gr[i][j] + gi[k][i] * gi[i][j];
+        ui = ui - gr[k][i] * gi[i][j] - gi[k][i] * gr[i][j];
+      }
+      gr[k][j] = ur;
+      gi[k][j] = ui;
+    }
+    if (k + 1 < N) {
+      double key = pivot_key(gr[k][k], gi[k][k], k);
+#pragma unroll
+      for (int j = k + 1; j < N; ++j) key = fmax(key, pivot_key(gr[k][j], gi[k][j], j));
+      int p = 7 - (int)(__double2loint(key) & 7u);
+      if (PIV == kThresholdPivot) {
+        const double dmag = fabs(gr[k][k]) + fabs(gi[k][k]);
+        if (dmag >= kThreshold * key) p = k;
+      }
+      // Exchange columns k and p in rows 0..k: column k's entries are
+      // saved, then for each candidate m the lanes that chose m move column
+      // m into column k and the saved entries into column m.
+      if (PIV == kPartialPivot || __builtin_amdgcn_ballot_w64(p != k) != 0) {
+        double tr[N], ti[N];
+        uint32_t tc = coloff[k];
+#pragma unroll
+        for (int i = 0; i <= k; ++i) {
+          tr[i] = gr[i][k];
+          ti[i] = gi[i][k];
+        }
+#pragma unroll
+        for (int m = k + 1; m < N; ++m) {
+          const uint64_t mask = __builtin_amdgcn_ballot_w64(p == m);
+          if (PIV == kThresholdPivot && mask == 0) continue;
+#pragma unroll
+          for (int i = 0; i <= k; i += 3) {
+            if (i + 2 <= k) {
+              double a6[6] = {gr[i][k], gi[i][k], gr[i + 1][k], gi[i + 1][k], gr[i + 2][k], gi[i + 2][k]};
+              double b6[6] = {gr[i][m], gi[i][m], gr[i + 1][m], gi[i + 1][m], gr[i + 2][m], gi[i + 2][m]};
+              double t6[6] = {tr[i], ti[i], tr[i + 1], ti[i + 1], tr[i + 2], ti[i + 2]};
+              masked_exchange3(mask, a6, b6, t6);
+#pragma unroll
+              for (int q = 0; q < 3; ++q) {
+                gr[i + q][k] = a6[2 * q];
+                gi[i + q][k] = a6[2 * q + 1];
+                gr[i + q][m] = b6[2 * q];
+                gi[i + q][m] = b6[2 * q + 1];
+                tr[i + q] = t6[2 * q];
+                ti[i + q] = t6[2 * q + 1];
+              }
+            } else {
+#pragma unroll
+              for (int ii = i; ii <= k; ++ii) {
+                double a2[2] = {gr[ii][k], gi[ii][k]};
+                double b2[2] = {gr[ii][m], gi[ii][m]};
+                double t2[2] = {tr[ii], ti[ii]};
+                masked_exchange1(mask, a2, b2, t2);
+                gr[ii][k] = a2[0];
+                gi[ii][k] = a2[1];
+                gr[ii][m] = b2[0];
+                gi[ii][m] = b2[1];
+                tr[ii] = t2[0];
+                ti[ii] = t2[1];
+              }
+            }
+          }
+          masked_exchange_u32(mask, coloff[k], coloff[m], tc);
+        }
+      }
+      neg = neg != (p != k);
+    }
+    const double pr = gr[k][k], pi = gi[k][k];
+    const double mag = fabs(pr) + fabs(pi);
+    zero_pivot = zero_pivot || (mag == 0.0);
+    const double t = sre * pr - sim * pi;
+    sim = sre * pi + sim * pr;
+    sre = t;
+    if (KEEP || k + 1 < N) {
+      double vr, vi;
+      cinv(pr, pi, mag, vr, vi);
+      if (KEEP) {
+        gr[k][k] = vr;
+        gi[k][k] = vi;
+      }
+      // Column k of L: l_m = (G[m][k] - sum_{i<k} L[m][i] U[i][k]) / U[k][k].
+#pragma unroll
+      for (int m = k + 1; m < N; ++m) {
+        const double2 v = *reinterpret_cast<const double2*>(lds + rowoff[m] + coloff[k]);
+        double ar = v.x, ai = v.y;
+#pragma unroll
+        for (int i = 0; i < k; ++i) {
+          ar = ar - gr[m][i] * gr[i][k] + gi[m][i] * gi[i][k];
+          ai = ai - gr[m][i] * gi[i][k] - gi[m][i] * gr[i][k];
+        }
+        gr[m][k] = ar * vr - ai * vi;
+        gi[m][k] = ar * vi + ai * vr;
+      }
+    }
+  }
+  dre = neg ? -sre : sre;
+  dim = neg ? -sim : sim;
+}
+
+// y = G^-1 e_R, in the column order of the factors of lu_crout<N, true>
+// (G Q = L U, so G^-1 e_R = Q U^-1 L^-1 e_R: entry m of y belongs to the
+// factors' column position m).  L^-1 e_R is zero above row R and 1 at R, so
+// the forward part starts there; R is a compile-time row.
+// Every entry of y depends on the first value formed (y_{R+1} of the
+// forward part, or y_{N-1} when R = N - 1).  That value passes through an
+// empty asm statement that also takes `tag`, a wave-uniform value that
+// changes from call to call in the caller's loop: the solve of every R is
+// loop-invariant for a given factorisation, and without the tie the
+// compiler hoists all N of them out of that loop (N solution vectors live
+// at once instead of the few solves needed).  The statement is not
+// volatile, so it is no memory access and the caller's loads of read-only
+// plan data stay scalar loads.
+template <int N, int R>
+__device__ __forceinline__ void solve_unit_col_r(const double (&gr)[N][N],
+                                                 const double (&gi)[N][N], int tag,
+                                                 double (&xr)[N], double (&xi)[N]) {
+#pragma unroll
+  for (int m = R + 1; m < N; ++m) {
+    double br = -gr[m][R], bi = -gi[m][R];
+#pragma unroll
+    for (int j = R + 1; j < m; ++j) {
+      br = br - gr[m][j] * xr[j] + gi[m][j] * xi[j];
+      bi = bi - gr[m][j] * xi[j] - gi[m][j] * xr[j];
+    }
+    if (m == R + 1) asm("" : "+v"(br), "+v"(bi) : "s"(tag));
+    xr[m] = br;
+    xi[m] = bi;
+  }
+#pragma unroll
+  for (int m = N - 1; m >= 0; --m) {
+    double br, bi;
+    int j0;
+    if (m > R) {
+      br = xr[m];
+      bi = xi[m];
+      j0 = m + 1;
+    } else if (m == R) {
+      br = 1.0;
+      bi = 0.0;
+      j0 = m + 1;
+      if (m == N - 1) asm("" : "+v"(br), "+v"(bi) : "s"(tag));
+    } else {
+      br = -(gr[m][m + 1] * xr[m + 1] - gi[m][m + 1] * xi[m + 1]);
+      bi = -(gr[m][m + 1] * xi[m + 1] + gi[m][m + 1] * xr[m + 1]);
+      j0 = m + 2;
+    }
+#pragma unroll
+    for (int j = j0; j < N; ++j) {
+      br = br - gr[m][j] * xr[j] + gi[m][j] * xi[j];
+      bi = bi - gr[m][j] * xi[j] - gi[m][j] * xr[j];
+    }
+    xr[m] = br * gr[m][m] - bi * gi[m][m];
+    xi[m] = br * gi[m][m] + bi * gr[m][m];
+  }
+}
+
+// The same for a wave-uniform runtime row r (0 <= r < N), followed by
+// use(xr, xi): one branch per row, each with its own structure and its own
+// copy of use, so that no solved vector has to be merged across branches.
+template <int N, int R = 0, typename Use>
+__device__ __forceinline__ void solve_unit_col(const double (&gr)[N][N],
+                                               const double (&gi)[N][N], int r, int tag,
+                                               Use&& use) {
+  if constexpr (R + 1 < N) {
+    if (r != R) {
+      solve_unit_col<N, R + 1>(gr, gi, r, tag, use);
+      return;
+    }
+  }
+  double xr[N], xi[N];
+  solve_unit_col_r<N, R>(gr, gi, tag, xr, xi);
+  use(xr, xi);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
