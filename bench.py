@@ -31,16 +31,16 @@ SETTLE_S = 0.3              # untimed work before the first timed method
 # HBM bytes per launch of the update-tree kernel on the mid workload, from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script
 # (--copy-probe), each scaled by the same counter's reading for a 256 MiB
-# device copy (fetch x 1.99973, write x 1.0).  Valid only for the kernel
+# device copy (fetch x 1.99972, write x 1.0).  Valid only for the kernel
 # sources they were measured on (SHA-256 below); null otherwise.
 TRAFFIC = {
     "workload": "mid",
-    "bytes": 5725.2 * 1.99973 * 1024 + 1120.0 * 1024,
+    "bytes": 7780.8 * 1.99972 * 1024 + 5216.0 * 1024,
     "sources": {
         "paper_1411_3691_amd/csrc/contract_kernels.hip":
-            "bc5b26980bb6a08384bb44f99a7fc3c6966a9b701933bdce6a5c5a429effaf9f",
+            "880b92fb3b12869b225efccf1476066c78d5fa010b4d19ba824912c832c8182a",
         "paper_1411_3691_amd/csrc/lu_device.h":
-            "f9244cc21145d9d84294f81c1218d1d79b6b5c7743f2c8a5a003337207fc11ac",
+            "3b5b2c5914bf701a7f937f97ce9876223e749d29c081dd58c93b9736918c6756",
         "paper_1411_3691_amd/csrc/contract_kernels.h":
             "bc0486545e82593f3f41324d36fe1545d163913d26540dbc00a6858f71a8445b",
     },

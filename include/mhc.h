@@ -79,9 +79,9 @@ enum {
   MHC_PLAIN_LU_UNPIVOTED = 3,
   MHC_UPDATE_TREE_UNPIVOTED = 4,
   /* Variants with threshold partial pivoting: the diagonal entry stays the
-   * pivot unless it is below 0.1 times the column's largest |Re|+|Im|
-   * (growth per step at most 11), so rows rarely move.  Every block must
-   * have one size n <= 8. */
+   * pivot unless it is below 0.1 times the largest |Re|+|Im| among the
+   * candidates (growth per step at most 11), so exchanges are rare.  Every
+   * block must have one size n <= 8. */
   MHC_PLAIN_LU_THRESHOLD = 5,
   MHC_UPDATE_TREE_THRESHOLD = 6
 };

@@ -174,12 +174,19 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
             for (int c = c_begin; c < c_end; ++c) {
               const uint32_t crow = uniform(p.child_rowoff[c]);
               const int cterm = uniform(p.child_term[c]);
+              // The child's N entries are read before any is used: without
+              // the scheduling barrier the compiler, short of registers,
+              // waits for each read before issuing the next.
+              double2 sv[N];
+#pragma unroll
+              for (int n = 0; n < N; ++n)
+                sv[n] = *reinterpret_cast<const double2*>(lds + crow + co[n]);
+              __builtin_amdgcn_sched_barrier(0);
               double rr = 0.0, ri = 0.0;
 #pragma unroll
               for (int n = 0; n < N; ++n) {
-                const double2 s = *reinterpret_cast<const double2*>(lds + crow + co[n]);
-                rr = rr + s.x * xr[n] - s.y * xi[n];
-                ri = ri + s.x * xi[n] + s.y * xr[n];
+                rr = rr + sv[n].x * xr[n] - sv[n].y * xi[n];
+                ri = ri + sv[n].x * xi[n] + sv[n].y * xr[n];
               }
               const double wc = a.w_src[cterm];
               sre += wc * rr;

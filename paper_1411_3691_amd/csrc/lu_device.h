@@ -70,8 +70,8 @@ __device__ __forceinline__ void gather(const char* lds, const uint32_t (&rowoff)
     }
 }
 
-// Row exchange in the lanes of `mask` only: a <- b, b <- t, where t holds
-// a's old value.  The EXEC mask is narrowed and restored inside one
+// Exchange of two rows (or columns) in the lanes of `mask` only: a <- b,
+// b <- t, where t holds a's old value.  The EXEC mask is narrowed and restored inside one
 // straight-line asm block, so the compiler sees no branch.  Every operand,
 // t included, is a read-write register operand: outputs never share a
 // register, so no value the block reads can sit in a register it has
