@@ -118,6 +118,14 @@ def test_repeatable_bitwise():
 def test_block_sizes_and_flavour_counts(nf, M, n_src, n_snk):
     w = W.workload("mid", T=2, M=M, nf=nf, n_src=n_src, n_snk=n_snk, branching=4, depth=3)
     plan, tree, S, ws, wk = setup(w)
+    # the lane kernels have one solve per changed row position r: with
+    # enough children every position of every flavour occurs
+    ex = tree.export()
+    child = ex["owner"] != np.arange(len(ex["owner"]))
+    for f, n in enumerate(nf):
+        in_f = child & (ex["flav"] == f)
+        if in_f.sum() >= 8 * n:
+            assert set(ex["pos"][in_f].tolist()) == set(range(n))
     for method in ("plain", "tree"):
         C, A, P = run(plan, S, ws, wk, method)
         check_pairs(w, P, *all_pairs(w))
