@@ -150,6 +150,26 @@ def two_sided_flops(T, nf, src_tree, snk_tree) -> float:
     return float(T) * total
 
 
+def fma_probe(dev, iters: int = 4096, n_blocks: int = 4096, reps: int = 10) -> float:
+    """Measured FP64 vector FMA rate (TFLOP/s) of this GPU: the probe kernel
+    of the library (16 independent v_fma_f64 chains per thread), timed with
+    HIP events on the launch stream over `reps` launches after 3 warm-ups."""
+    import torch
+    from paper_1411_3691_amd import mhc
+    out = torch.empty(n_blocks * mhc.PROBE_BLOCK, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        mhc.probe_fma64(out, iters)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    flop = 0
+    for _ in range(reps):
+        flop += mhc.probe_fma64(out, iters)
+    e1.record()
+    torch.cuda.synchronize()
+    return flop / (e0.elapsed_time(e1) * 1e-3) / 1e12
+
+
 def plain_flops(T, n_src, n_snk, nf) -> float:
     return float(T) * n_src * n_snk * (sum(f_lu(n) for n in nf) + 11)
 
@@ -348,6 +368,8 @@ def main():
         mhc.contract_into(plan, S, ws, wk, C, "tree")
         torch.cuda.synchronize()
 
+    probe = fma_probe(dev)
+
     def timed(method):
         for _ in range(args.warmup):
             mhc.contract_into(plan, S, ws, wk, C, method)
@@ -483,6 +505,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(args.workload)},
+        "fp64_fma_probe": {"tflops": probe, "frac_of_peak": probe / FP64_PEAK_TFLOPS,
+                           "tree_frac_of_probe": ach / probe},
         "cpu_baseline": cpu,
         "two_sided": two,
         "ablations": abl,

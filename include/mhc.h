@@ -272,6 +272,21 @@ mhc_status mhc_batch_info(const mhc_batch* batch, int32_t* n_tiles, int32_t* n_k
                           int64_t* n_pairs);
 void mhc_batch_destroy(mhc_batch* batch);
 
+/* Device probe (not an operation of the paper): the FP64 vector FMA rate
+ * that the roofline of the contraction kernels is set against, measured on
+ * the current device.  Launches n_blocks workgroups of 256 threads on
+ * `stream`; every thread runs `iters` rounds of 16 independent fused
+ * multiply-adds a <- a * b + c (32 flop per round) in registers and writes
+ * the sum of its 16 values to out[thread].  The caller times the launch:
+ * flop per launch = n_blocks * 256 * iters * 32.
+ *   out   device, double [n_blocks * 256], caller-owned;
+ *   chain values: a_0 = 1 + i / 1024 (i = 0..15), b = 1 - 2^-20,
+ *   c = 2^-30 * (1 + (threadIdx & 7)), so out[thread] equals
+ *   sum_i (b^iters a_0 + c (1 - b^iters) / (1 - b)) up to rounding.
+ * Errors: MHC_E_ARG (NULL out, n_blocks outside [1, 2^20], iters outside
+ * [1, 2^24]), MHC_E_DEVICE (launch failure). */
+mhc_status mhc_probe_fma64(double* out, int32_t n_blocks, int32_t iters, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

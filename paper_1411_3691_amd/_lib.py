@@ -71,6 +71,7 @@ SIGNATURES = {
                              ctypes.POINTER(_P), ctypes.POINTER(_P), _P]),
     "mhc_batch_info": (_I32, [_P, _PI32, _PI32, _PI64]),
     "mhc_batch_destroy": (None, [_P]),
+    "mhc_probe_fma64": (_I32, [_PD, _I32, _I32, _P]),
 }
 
 

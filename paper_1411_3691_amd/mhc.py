@@ -195,6 +195,24 @@ def contract_into(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch
         _stream_ptr()))
 
 
+PROBE_BLOCK = 256
+PROBE_FLOP_PER_ROUND = 32
+
+
+def probe_fma64(out: torch.Tensor, iters: int) -> int:
+    """Enqueue the FP64 FMA probe (mhc_probe_fma64) on torch's current
+    stream: out (float64, a multiple of 256 entries, on a GPU) gets one
+    value per thread.  Returns the flop count of the launch."""
+    if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 GPU tensor")
+    if out.numel() == 0 or out.numel() % PROBE_BLOCK:
+        raise ValueError(f"out must hold a positive multiple of {PROBE_BLOCK} values")
+    n_blocks = out.numel() // PROBE_BLOCK
+    check(lib().mhc_probe_fma64(ctypes.c_void_p(out.data_ptr()), n_blocks, iters,
+                                _stream_ptr()))
+    return out.numel() * iters * PROBE_FLOP_PER_ROUND
+
+
 def contract(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch.Tensor,
              method: str = "tree", with_scale: bool = False, with_pairs: bool = False):
     """C(t) for every slice (complex128 [T] on the plan's device).  With

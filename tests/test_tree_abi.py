@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "mhc.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mhc_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(mhc_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -28,7 +28,15 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
-    assert L.mhc_version() >= 200
+    assert L.mhc_version() >= 201
+    assert "mhc_probe_fma64" in names
+
+
+def test_probe_rejects_bad_arguments_before_launching():
+    # host-side checks only: nothing is enqueued on these paths
+    L = _lib.lib()
+    E_ARG = -1
+    assert L.mhc_probe_fma64(None, 1, 1, None) == E_ARG
 
 
 def tree_matches_oracle(terms, nf, M, policy):
