@@ -12,9 +12,9 @@
 //
 // Work decomposition: a workgroup owns (slice t, sink block of 64) and walks
 // every source term (wave w takes sources w, w+4, ...); lane l = sink
-// 64*block + l.  S_t and an accumulator for grad S_t live in LDS; the
-// accumulator takes LDS atomic adds (FP64), then goes to a per-workgroup
-// partial that fixed-order kernels reduce.  The weight gradients are reduced
+// block + l * (number of blocks) (adj_sink).  S_t and an accumulator for
+// grad S_t live in LDS; the accumulator takes LDS atomic adds (FP64), then
+// goes to a per-workgroup partial that fixed-order kernels reduce.  The weight gradients are reduced
 // in a fixed order (bitwise repeatable); grad S is repeatable up to the
 // order of the LDS atomics within one workgroup.
 
@@ -29,6 +29,33 @@ namespace mhc {
 namespace kern {
 
 constexpr int kMaxAdjFlavors = 4;
+
+// Sink of lane `lane` in sink block sb: the blocks take the sinks with a
+// stride of n_sblk, not 64 consecutive sinks.  Neighbouring sinks of a
+// tree-ordered list are siblings that share most of their column indices;
+// in one wave their cofactors would be added to the same grad S entries,
+// and LDS atomic adds to one address from several lanes serialise.
+__device__ __forceinline__ int adj_sink(int sb, int lane, int n_sblk) {
+  return sb + n_sblk * lane;
+}
+
+// The LDS accumulator of grad S_t holds the real parts and the imaginary
+// parts in two planes of M x (M + 1) doubles (`plane` bytes apart), entry
+// (row, col) at (row * (M + 1) + col) * 8: half the byte offset of the same
+// entry in the complex copy of S_t, so the plan's row and column offsets
+// serve both.  With 8-byte steps between columns, 64-bit atomics of lanes
+// that add to different columns of one row spread over all LDS bank pairs
+// (complex entries, 16 bytes apart, would use every other pair).
+__host__ __device__ constexpr uint32_t grad_plane_bytes(int M) {
+  return (uint32_t)M * lds_row(M) * 8;
+}
+
+__device__ __forceinline__ void grad_add(char* glds, uint32_t plane, uint32_t rowoff,
+                                         uint32_t coloff, double re, double im) {
+  char* e = glds + ((rowoff + coloff) >> 1);
+  atomicAdd(reinterpret_cast<double*>(e), re);
+  atomicAdd(reinterpret_cast<double*>(e + plane), im);
+}
 
 // One source term against the lane's sink, pair by pair: the term's rows
 // are the row set `rowoff` with, in flavour fs, row rs replaced by the row
@@ -116,11 +143,7 @@ __device__ __forceinline__ double2 member_adjoint(const PlanView& p, const char*
         // grad S[row r][col n] += b * conj(x[n])
         const double vr = bre * xr[n] + bim * xi[n];
         const double vi = bim * xr[n] - bre * xi[n];
-        double* dst = reinterpret_cast<double*>(glds + ro[r] + co[n]);
-        if (valid) {
-          atomicAdd(dst, vr);
-          atomicAdd(dst + 1, vi);
-        }
+        if (valid) grad_add(glds, grad_plane_bytes(p.M), ro[r], co[n], vr, vi);
       }
     }
   }
@@ -157,12 +180,16 @@ __device__ __forceinline__ void adjoint_finish(const AdjointArgs& a, int t, int 
     double v = 0.0;
 #pragma unroll
     for (int w = 0; w < kWavesPerBlock; ++w) v += red[w][threadIdx.x];
-    a.part_wsnk[(size_t)t * p.n_snk_pad + sb * kWave + threadIdx.x] = v;
+    a.part_wsnk[(size_t)t * p.n_snk_pad + adj_sink(sb, threadIdx.x, a.n_sblk)] = v;
   }
   const int MM = p.M * p.M;
-  const double2* gl = smem + p.M * lds_row(p.M);
+  const double* re = reinterpret_cast<const double*>(smem + p.M * lds_row(p.M));
+  const double* im = re + p.M * lds_row(p.M);
   double2* dst = a.part_gS + ((size_t)t * a.n_sblk + sb) * MM;
-  for (int e = threadIdx.x; e < MM; e += kBlock) dst[e] = gl[(e / p.M) * lds_row(p.M) + e % p.M];
+  for (int e = threadIdx.x; e < MM; e += kBlock) {
+    const int q = (e / p.M) * lds_row(p.M) + e % p.M;
+    dst[e] = make_double2(re[q], im[q]);
+  }
 }
 
 // Plain adjoint: every source term, pair by pair.
@@ -177,7 +204,7 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_kernel(AdjointArgs a) {
   adjoint_stage(a, t, smem);
   const char* lds = reinterpret_cast<const char*>(smem);
   char* glds = reinterpret_cast<char*>(smem + p.M * lds_row(p.M));
-  const int k = sb * kWave + lane;
+  const int k = adj_sink(sb, lane, a.n_sblk);
   const bool valid = k < p.n_snk;
   const double wk = valid ? a.w_snk[k] : 0.0;
   const double2 gc = a.gC[t];
@@ -221,7 +248,8 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
   adjoint_stage(a, t, smem);
   const char* lds = reinterpret_cast<const char*>(smem);
   char* glds = reinterpret_cast<char*>(smem + p.M * lds_row(p.M));
-  const int k = sb * kWave + lane;
+  const uint32_t plane = grad_plane_bytes(p.M);
+  const int k = adj_sink(sb, lane, a.n_sblk);
   const bool valid = k < p.n_snk;
   const double wk = valid ? a.w_snk[k] : 0.0;
   const double2 gc = a.gC[t];
@@ -340,11 +368,7 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
         for (int n = 0; n < N; ++n) {
           const double vr = Wre * xr[n] - Wim * xi[n];
           const double vi = Wre * xi[n] + Wim * xr[n];
-          double* dst = reinterpret_cast<double*>(glds + ro[m] + co[n]);
-          if (fast) {
-            atomicAdd(dst, bre * vr + bim * vi);
-            atomicAdd(dst + 1, bim * vr - bre * vi);
-          }
+          if (fast) grad_add(glds, plane, ro[m], co[n], bre * vr + bim * vi, bim * vr - bre * vi);
         }
         // the group that changes row m, if any (groups are sorted by row)
         if (gg < g_f_end && uniform(p.grp_fr[gg] & 0xff) == m) {
@@ -386,11 +410,9 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
             // the child's own row: w_c x_m[n] at (new row, column n)
 #pragma unroll
             for (int n = 0; n < N; ++n) {
-              double* dst = reinterpret_cast<double*>(glds + crow + co[n]);
-              if (fast) {
-                atomicAdd(dst, wc * (bre * xr[n] + bim * xi[n]));
-                atomicAdd(dst + 1, wc * (bim * xr[n] - bre * xi[n]));
-              }
+              if (fast)
+                grad_add(glds, plane, crow, co[n], wc * (bre * xr[n] + bim * xi[n]),
+                         wc * (bim * xr[n] - bre * xi[n]));
             }
           }
           // - Z_r x_r^T on the dominator's rows (Z in pivot order: entry j
@@ -401,11 +423,8 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
             for (int n = 0; n < N; ++n) {
               const double vr = -(Zr[j] * xr[n] - Zi[j] * xi[n]);
               const double vi = -(Zr[j] * xi[n] + Zi[j] * xr[n]);
-              double* dst = reinterpret_cast<double*>(glds + prow[j] + co[n]);
-              if (fast) {
-                atomicAdd(dst, bre * vr + bim * vi);
-                atomicAdd(dst + 1, bim * vr - bre * vi);
-              }
+              if (fast)
+                grad_add(glds, plane, prow[j], co[n], bre * vr + bim * vi, bim * vr - bre * vi);
             }
           ++gg;
         }
