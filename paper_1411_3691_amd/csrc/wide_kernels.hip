@@ -22,6 +22,19 @@
 // tree structure stays wave-uniform); a workgroup stages S_t in LDS and its
 // waves walk a strided share of the slice's items, as in the one-lane-per-
 // matrix kernels.  Reductions are fixed-order.
+//
+// Broadcasts within a group: in the 1024-thread workgroups (four waves
+// per SIMD, where the LDS pipe bounds the elimination) they go through
+// LDS: the pivot lane writes its row to the group's row buffer and every
+// lane of the group reads it back (one ds_read_b128 per complex entry, all
+// lanes of a group on one address).  On gfx950 that moves about 270 B per
+// clock and compute unit against about 40 for ds_bpermute_b32, which needs
+// four instructions per complex entry.  The row buffers sit at the start
+// of the dynamic LDS, the copy of S_t after them.  In the 512-thread
+// workgroups (two waves per SIMD, where the latency of each elimination
+// step bounds it) the shuffles stay: the write-then-read of the buffer
+// lengthens that chain (measured 17 % slower there, 3-11 % faster in the
+// 1024-thread kernels).
 
 #include <hip/hip_runtime.h>
 
@@ -39,6 +52,15 @@ namespace kern {
 // four waves per SIMD hide the broadcast latencies of the elimination.
 constexpr int kWideBlock = 512;
 constexpr int kWideBlockBig = 1024;
+
+// Broadcast through LDS row buffers (true) or shuffles, per workgroup size.
+constexpr bool wide_lds_bcast(int wb) { return wb == kWideBlockBig; }
+
+// Bytes of the groups' row buffers of one workgroup: NMAX complex entries
+// per group, where the broadcast goes through LDS.
+constexpr size_t wide_rows_bytes(int group, int nmax, int wb) {
+  return wide_lds_bcast(wb) ? (size_t)(wb / group) * nmax * 16 : 0;
+}
 
 // A double moved across lanes by a DPP row rotation (within each row of 16
 // lanes): lane i receives lane (i + R) mod 16 of its row.
@@ -75,6 +97,18 @@ __device__ __forceinline__ double group_max(double v) {
   return v;
 }
 
+// The lanes of a group exchange values through LDS with plain stores and
+// loads.  Between a lane's store and another lane's load (and between a
+// load and the next store to the same place) the compiler must not move
+// either: a wavefront-scope release/acquire fence around a wave barrier
+// forbids that.  LDS executes one wave's instructions in order, so it
+// costs nothing at run time.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // fn(integral_constant<int, i>) for i = B .. E-1: the loop is unrolled in
 // the source, so every array index below is a constant expression and the
 // per-lane rows stay in registers at any NMAX.
@@ -106,10 +140,15 @@ struct PivotLanes {
 // on any right-hand side afterwards (replay_unit).  On return, lane m < n
 // holds the reciprocal of its pivot in (ur, ui) and the column it pivoted
 // in (col); piv holds the pivot lane of every step.
-template <int GROUP, int NMAX>
+// LDS_BCAST: the pivot row goes through the group's LDS row buffer (the
+// factorisations of the main path); otherwise through ds_bpermute shuffles
+// (the direct factorisations of the zero-pivot route, where the LDS form,
+// inlined into the children loop, made the compiler keep far more
+// registers live).
+template <int GROUP, int NMAX, bool LDS_BCAST>
 __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai)[NMAX], int n,
                                                  int m, double& ur, double& ui, int& col,
-                                                 PivotLanes<NMAX>& piv) {
+                                                 PivotLanes<NMAX>& piv, double2* prow) {
   static_assert(GROUP <= 32, "lane rank is packed into 5 bits");
   GJResult res{1.0, 0.0, false};
   bool done = m >= n;
@@ -137,9 +176,24 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
     const uint32_t below = (uint32_t)((open >> gbase) & ((1ull << p) - 1ull));
     neg = neg != ((__builtin_popcount(below) & 1) != 0);
     // pivot row, broadcast to the group
+    const bool me = (m == p);
     const int src = gbase + p;
-    const double pr = __shfl(ar[k], src, 64);
-    const double pi = __shfl(ai[k], src, 64);
+    double pr, pi;
+    if constexpr (LDS_BCAST) {
+      if (me) {
+        static_for<k, NMAX>([&](auto cc) {
+          constexpr int c = decltype(cc)::value;
+          if (c < n) prow[c] = make_double2(ar[c], ai[c]);
+        });
+      }
+      wave_lds_sync();
+      const double2 pv = prow[k];
+      pr = pv.x;
+      pi = pv.y;
+    } else {
+      pr = __shfl(ar[k], src, 64);
+      pi = __shfl(ai[k], src, 64);
+    }
     const double pmag = fabs(pr) + fabs(pi);
     res.zero = res.zero || (pmag == 0.0);
     const double t = res.dre * pr - res.dim * pi;
@@ -147,7 +201,6 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
     res.dre = t;
     double vr, vi;
     cinv(pr, pi, pmag, vr, vi);
-    const bool me = (m == p);
     if (me) {
       ur = vr;
       ui = vi;
@@ -164,11 +217,19 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
     static_for<k + 1, NMAX>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
       if (c >= n) return;
-      const double br = __shfl(ar[c], src, 64);
-      const double bi = __shfl(ai[c], src, 64);
+      double br, bi;
+      if constexpr (LDS_BCAST) {
+        const double2 b = prow[c];
+        br = b.x;
+        bi = b.y;
+      } else {
+        br = __shfl(ar[c], src, 64);
+        bi = __shfl(ai[c], src, 64);
+      }
       ar[c] = ar[c] - lr * br + li * bi;
       ai[c] = ai[c] - lr * bi - li * br;
     });
+    if constexpr (LDS_BCAST) wave_lds_sync();   // the row is read before the next step writes
     if (!me) {
       ar[k] = lr;
       ai[k] = li;
@@ -185,18 +246,30 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
 // column e_r (lane m holds entry m); then x[col_m] = E'_m / u_m, returned
 // in (xr, xi) by lane m.  The pivot lane of a step keeps its own column k
 // entry (its pivot), which the step does not use.
-template <int GROUP, int NMAX>
+template <int GROUP, int NMAX, bool LDS_BCAST>
 __device__ __forceinline__ void replay_unit(const double (&ar)[NMAX], const double (&ai)[NMAX],
                                             const PivotLanes<NMAX>& piv, int r, int n, int m,
-                                            double ur, double ui, double& xr, double& xi) {
+                                            double ur, double ui, double& xr, double& xi,
+                                            double2* prow) {
   const int gbase = (__lane_id() / GROUP) * GROUP;
   double er = (m == r) ? 1.0 : 0.0, ei = 0.0;
   static_for<0, NMAX>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     if (k >= n) return;
     const int p = piv.get(k);
-    const double br = __shfl(er, gbase + p, 64);
-    const double bi = __shfl(ei, gbase + p, 64);
+    // the pivot lane's entry, broadcast to the group
+    double br, bi;
+    if constexpr (LDS_BCAST) {
+      if (m == p) prow[0] = make_double2(er, ei);
+      wave_lds_sync();
+      const double2 b = prow[0];
+      wave_lds_sync();
+      br = b.x;
+      bi = b.y;
+    } else {
+      br = __shfl(er, gbase + p, 64);
+      bi = __shfl(ei, gbase + p, 64);
+    }
     if (m != p && m < n) {
       er = er - ar[k] * br + ai[k] * bi;
       ei = ei - ar[k] * bi - ai[k] * br;
@@ -211,7 +284,8 @@ __device__ __forceinline__ void replay_unit(const double (&ar)[NMAX], const doub
 template <int GROUP, int NMAX>
 __device__ __forceinline__ void block_det_direct(const char* lds, uint32_t myrow, int rrep,
                                                  uint32_t newrow, const uint32_t (&co)[NMAX],
-                                                 int n, int m, double& dre, double& dim) {
+                                                 int n, int m, double& dre, double& dim,
+                                                 double2* prow) {
   const uint32_t row = (m == rrep) ? newrow : myrow;
   double ar[NMAX], ai[NMAX];
 #pragma unroll
@@ -227,7 +301,7 @@ __device__ __forceinline__ void block_det_direct(const char* lds, uint32_t myrow
   double ur, ui;
   int col;
   PivotLanes<NMAX> piv;
-  const GJResult g = gauss_jordan<GROUP, NMAX>(ar, ai, n, m, ur, ui, col, piv);
+  const GJResult g = gauss_jordan<GROUP, NMAX, false>(ar, ai, n, m, ur, ui, col, piv, prow);
   dre = g.dre;
   dim = g.dim;
 }
@@ -248,9 +322,13 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
   const int MM = p.M * p.M;
   const double2* St = a.S + (size_t)t * MM;
   constexpr int kWaves = WB / kWave;
-  stage_slice(St, smem, p.M, WB);
+  // this group's row buffer (used with LDS broadcasts only), then the copy
+  // of S_t
+  double2* prow = smem + (threadIdx.x / GROUP) * NMAX;
+  double2* slice = smem + wide_rows_bytes(GROUP, NMAX, WB) / 16;
+  stage_slice(St, slice, p.M, WB);
   __syncthreads();
-  const char* lds = reinterpret_cast<const char*>(smem);
+  const char* lds = reinterpret_cast<const char*>(slice);
 
   double acc_re = 0.0, acc_im = 0.0, acc_a = 0.0;
   uint32_t n_fallback = 0;
@@ -293,7 +371,8 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
           for (int c = 0; c < NMAX; ++c)
             co[c] = c < n ? p.snk_coloff[(size_t)(o + c) * p.n_snk_pad + k] : 0u;
           const uint32_t myrow = m < n ? rowoff_d[o + m] : 0u;
-          block_det_direct<GROUP, NMAX>(lds, myrow, -1, 0u, co, n, m, Dpre_re[f], Dpre_im[f]);
+          block_det_direct<GROUP, NMAX>(lds, myrow, -1, 0u, co, n, m, Dpre_re[f], Dpre_im[f],
+                                        prow);
         }
       }
     }
@@ -326,7 +405,8 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
       double ur, ui;
       int col;
       PivotLanes<NMAX> piv;
-      const GJResult res = gauss_jordan<GROUP, NMAX>(ar, ai, n, m, ur, ui, col, piv);
+      const GJResult res =
+          gauss_jordan<GROUP, NMAX, wide_lds_bcast(WB)>(ar, ai, n, m, ur, ui, col, piv, prow);
       const double dre = res.dre, dim = res.dim;
       const bool zero = res.zero;
       // this lane's pivot column: its sink column offset
@@ -340,8 +420,9 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
         for (int q = 0; q < R; ++q) {
           // x = G^-1 e_r for this group's row r; lane m holds x[col]
           double x_r, x_i;
-          replay_unit<GROUP, NMAX>(ar, ai, piv, uniform(p.grp_fr[g + q] & 0xff), n, m, ur, ui,
-                                   x_r, x_i);
+          replay_unit<GROUP, NMAX, wide_lds_bcast(WB)>(ar, ai, piv,
+                                                       uniform(p.grp_fr[g + q] & 0xff), n, m,
+                                                       ur, ui, x_r, x_i, prow);
           const int gg = g + q;
           const int c_begin = uniform(p.grp_ptr[gg]);
           const int c_end = uniform(p.grp_ptr[gg + 1]);
@@ -416,7 +497,7 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
               const uint32_t crow = uniform(p.child_rowoff[c]);
               const int cterm = uniform(p.child_term[c]);
               double cre, cim;
-              block_det_direct<GROUP, NMAX>(lds, myrow, r, crow, co, n, m, cre, cim);
+              block_det_direct<GROUP, NMAX>(lds, myrow, r, crow, co, n, m, cre, cim, prow);
               if (need && fbad == f) {
                 const double wc = a.w_src[cterm];
                 fre += wc * cre;
@@ -496,14 +577,23 @@ constexpr bool big_block_allowed(int nmax, bool tree, int mode) {
   return (mode & 2) == 0 && (!tree || nmax <= 12);
 }
 
+// The LDS a workgroup can have: 160 KiB, less 1 KiB for the static
+// arrays of the kernels.
+constexpr size_t kWideLdsLimit = 159 * 1024;
+
 int wide_block(int nmax, bool tree, size_t lds) {
   if (lds <= 80 * 1024) return kWideBlock;
-  return big_block_allowed(wide_bucket(nmax), tree, 0) ? kWideBlockBig : kWideBlock;
+  const int b = wide_bucket(nmax);
+  const int group = b <= 16 ? 16 : 32;
+  if (!big_block_allowed(b, tree, 0)) return kWideBlock;
+  return lds + wide_rows_bytes(group, b, kWideBlockBig) <= kWideLdsLimit ? kWideBlockBig
+                                                                         : kWideBlock;
 }
 
 template <int GROUP, int NMAX, bool TREE, int MODE, int WB>
-static hipError_t launch_wide_wb(const ContractArgs& a, size_t lds, hipStream_t s) {
+static hipError_t launch_wide_wb(const ContractArgs& a, size_t slice, hipStream_t s) {
   dim3 grid(a.n_blk_t, a.T);
+  const size_t lds = slice + wide_rows_bytes(GROUP, NMAX, WB);
   hipError_t e = hipFuncSetAttribute(
       reinterpret_cast<const void*>(&contract_wide_kernel<GROUP, NMAX, TREE, MODE, WB>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -535,7 +625,9 @@ static hipError_t launch_wide_n(const ContractArgs& a, bool tree, bool diag, hip
 int wide_sinks_per_wave(int nmax) { return nmax <= 16 ? kWave / 16 : kWave / 32; }
 
 template <int GROUP, int NMAX, bool TREE, int MODE, int WB>
-static hipError_t launch_batch_wide_wb(const BatchArgs& b, int grid, size_t lds, hipStream_t s) {
+static hipError_t launch_batch_wide_wb(const BatchArgs& b, int grid, size_t slice,
+                                       hipStream_t s) {
+  const size_t lds = slice + wide_rows_bytes(GROUP, NMAX, WB);
   hipError_t e = hipFuncSetAttribute(
       reinterpret_cast<const void*>(&batch_wide_kernel<GROUP, NMAX, TREE, MODE, WB>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
