@@ -52,6 +52,9 @@ namespace kern {
 // four waves per SIMD hide the broadcast latencies of the elimination.
 constexpr int kWideBlock = 512;
 constexpr int kWideBlockBig = 1024;
+// 768 threads: three waves per SIMD for the tree's buckets of blocks above
+// 12 (they need about 170 VGPRs: two waves per SIMD at 512 threads).
+constexpr int kWideBlockMid = 768;
 
 // Broadcast through LDS row buffers (true) or shuffles, per workgroup size.
 constexpr bool wide_lds_bcast(int wb) { return wb == kWideBlockBig; }
@@ -577,13 +580,18 @@ constexpr bool big_block_allowed(int nmax, bool tree, int mode) {
   return (mode & 2) == 0 && (!tree || nmax <= 12);
 }
 
+constexpr bool mid_block_allowed(int nmax, bool tree, int mode) {
+  return (mode & 2) == 0 && tree && nmax > 12;
+}
+
 // The LDS a workgroup can have: 160 KiB, less 1 KiB for the static
 // arrays of the kernels.
 constexpr size_t kWideLdsLimit = 159 * 1024;
 
 int wide_block(int nmax, bool tree, size_t lds) {
-  if (lds <= 80 * 1024) return kWideBlock;
   const int b = wide_bucket(nmax);
+  if (mid_block_allowed(b, tree, 0)) return kWideBlockMid;
+  if (lds <= 80 * 1024) return kWideBlock;
   const int group = b <= 16 ? 16 : 32;
   if (!big_block_allowed(b, tree, 0)) return kWideBlock;
   return lds + wide_rows_bytes(group, b, kWideBlockBig) <= kWideLdsLimit ? kWideBlockBig
@@ -609,6 +617,10 @@ static hipError_t launch_wide_one(const ContractArgs& a, hipStream_t s) {
   if constexpr (big_block_allowed(NMAX, TREE, MODE)) {
     if (wide_block(NMAX, TREE, lds) == kWideBlockBig)
       return launch_wide_wb<GROUP, NMAX, TREE, MODE, kWideBlockBig>(a, lds, s);
+  }
+  if constexpr (mid_block_allowed(NMAX, TREE, MODE)) {
+    if (wide_block(NMAX, TREE, lds) == kWideBlockMid)
+      return launch_wide_wb<GROUP, NMAX, TREE, MODE, kWideBlockMid>(a, lds, s);
   }
   return launch_wide_wb<GROUP, NMAX, TREE, MODE, kWideBlock>(a, lds, s);
 }
@@ -642,6 +654,10 @@ static hipError_t launch_batch_wide_m(const BatchArgs& b, int grid, size_t lds, 
   if constexpr (big_block_allowed(NMAX, TREE, MODE)) {
     if (wide_block(NMAX, TREE, lds) == kWideBlockBig)
       return launch_batch_wide_wb<GROUP, NMAX, TREE, MODE, kWideBlockBig>(b, grid, lds, s);
+  }
+  if constexpr (mid_block_allowed(NMAX, TREE, MODE)) {
+    if (wide_block(NMAX, TREE, lds) == kWideBlockMid)
+      return launch_batch_wide_wb<GROUP, NMAX, TREE, MODE, kWideBlockMid>(b, grid, lds, s);
   }
   return launch_batch_wide_wb<GROUP, NMAX, TREE, MODE, kWideBlock>(b, grid, lds, s);
 }
