@@ -45,6 +45,30 @@ def test_wide_blocks_all_pairs(nf, M, n_src, n_snk):
         check_C(C, A, Cw, Aw)
 
 
+@pytest.mark.parametrize("nf,n_src,n_snk", [
+    ((3, 5), 60, 23),       # uneven blocks below 8
+    ((12, 12), 60, 17),
+    ((16,), 50, 13),
+    ((9, 17), 40, 9),
+    ((18, 2), 40, 9),
+    ((24,), 16, 5),
+])
+def test_wide_blocks_with_m96_slices(nf, n_src, n_snk):
+    # a 96-index slice (147 KB of LDS, one workgroup per compute unit)
+    # selects the 1024-thread kernels, whose pivot rows go through LDS row
+    # buffers, and for the tree's blocks above 12 the 768-thread kernels;
+    # every pair against the oracle
+    w = W.workload("mid", T=2, M=96, nf=nf, n_src=n_src, n_snk=n_snk, branching=4, depth=3)
+    plan, S, ws, wk = setup(w)
+    Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+    for method in ("plain", "tree"):
+        C, A, P = run(plan, S, ws, wk, method)
+        check_pairs(w, P, *all_pairs(w))
+        check_C(C, A, Cw, Aw)
+        Cf = mhc.contract(plan, S, ws, wk, method).cpu().numpy()
+        assert np.all(np.abs(Cf - C) <= 1e-12 * Aw)
+
+
 def test_large_shape_subset():
     # 96 quark indices (a 147 KB slice in LDS), blocks of 12, tree terms with
     # branching 16 and depth <= 5; 3 slices, 400 x 130 terms
