@@ -52,8 +52,8 @@ namespace kern {
 // four waves per SIMD hide the broadcast latencies of the elimination.
 constexpr int kWideBlock = 512;
 constexpr int kWideBlockBig = 1024;
-// 768 threads: three waves per SIMD for the tree's buckets of blocks above
-// 12 (they need about 170 VGPRs: two waves per SIMD at 512 threads).
+// 768 threads: three waves per SIMD for the kernels that need 129..168
+// VGPRs (two waves per SIMD at 512 threads).
 constexpr int kWideBlockMid = 768;
 
 // Broadcast through LDS row buffers (true) or shuffles, per workgroup size.
@@ -580,8 +580,10 @@ constexpr bool big_block_allowed(int nmax, bool tree, int mode) {
   return (mode & 2) == 0 && (!tree || nmax <= 12);
 }
 
+// The buckets that need 129..168 VGPRs: the tree's from 12 up, the plain
+// 16 and 24.
 constexpr bool mid_block_allowed(int nmax, bool tree, int mode) {
-  return (mode & 2) == 0 && tree && nmax > 12;
+  return (mode & 2) == 0 && (tree ? nmax >= 12 : (nmax == 16 || nmax == 24));
 }
 
 // The LDS a workgroup can have: 160 KiB, less 1 KiB for the static
@@ -590,12 +592,14 @@ constexpr size_t kWideLdsLimit = 159 * 1024;
 
 int wide_block(int nmax, bool tree, size_t lds) {
   const int b = wide_bucket(nmax);
-  if (mid_block_allowed(b, tree, 0)) return kWideBlockMid;
-  if (lds <= 80 * 1024) return kWideBlock;
   const int group = b <= 16 ? 16 : 32;
-  if (!big_block_allowed(b, tree, 0)) return kWideBlock;
-  return lds + wide_rows_bytes(group, b, kWideBlockBig) <= kWideLdsLimit ? kWideBlockBig
-                                                                         : kWideBlock;
+  // one slice fills most of the LDS (one workgroup per compute unit): 1024
+  // threads where the kernel fits 128 VGPRs and the row buffers fit
+  if (lds > 80 * 1024 && big_block_allowed(b, tree, 0) &&
+      lds + wide_rows_bytes(group, b, kWideBlockBig) <= kWideLdsLimit)
+    return kWideBlockBig;
+  if (mid_block_allowed(b, tree, 0)) return kWideBlockMid;
+  return kWideBlock;
 }
 
 template <int GROUP, int NMAX, bool TREE, int MODE, int WB>
