@@ -40,8 +40,9 @@
 namespace mhc {
 namespace kern {
 
-// x = G^-1 v in place from the factors of lu<N, true>, with (vr, vi) = P v
-// on entry (v permuted to pivot order): L y = P v, then U x = y.
+// x' = U^-1 L^-1 v in place from the factors of lu_crout<N, true> (G Q =
+// L U, diagonal holding 1/U_mm): G^-1 v = Q x', so entry m of x' belongs
+// to the factors' column position m.
 template <int N>
 __device__ __forceinline__ void solve_col(const double (&gr)[N][N], const double (&gi)[N][N],
                                           double (&vr)[N], double (&vi)[N]) {
@@ -134,49 +135,44 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
 #pragma unroll
       for (int m = 0; m < N; ++m) ro[m] = rowoff_d[o + m];
       double gr[N][N], gi[N][N];
-      int perm[N];
       bool zero;
       double dre, dim;
-      gather<N>(lds, ro, co, gr, gi);
-      lu<N, true>(gr, gi, dre, dim, perm, zero);
+      // Crout LU with column pivoting (G Q = L U): rows stay in place, co
+      // comes back in the factors' column order
+      lu_crout<N, true, kPartialPivot>(lds, ro, co, gr, gi, dre, dim, zero);
       bad = bad || zero;
       {
         const double tr = Pre * dre - Pim * dim;
         Pim = Pre * dim + Pim * dre;
         Pre = tr;
       }
-      // row offset of the original row now at position m
-      uint32_t prow[N];
-#pragma unroll
-      for (int m = 0; m < N; ++m) {
-        uint32_t v = ro[0];
-#pragma unroll
-        for (int j = 1; j < N; ++j)
-          if (perm[m] == j) v = ro[j];
-        prow[m] = v;
-      }
       // the source groups of flavour f (wave-uniform): x_r, rho_c
       int g_f_end = g;
       while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
       for (int gg = g; gg < g_f_end; ++gg) {
         const int r = uniform(p.grp_fr[gg] & 0xff);
-        double xr[N], xi[N];
-        solve_unit<N>(gr, gi, perm, r, xr, xi);
         const int c_begin = uniform(p.grp_ptr[gg]);
         const int c_end = uniform(p.grp_ptr[gg + 1]);
-        for (int c = c_begin; c < c_end; ++c) {
-          const uint32_t crow = uniform(p.child_rowoff[c]);
-          const double wc = a.w_src[uniform(p.child_term[c])];
-          double rr = 0.0, ri = 0.0;
+        // x_r in the factors' column order, the order of co
+        solve_unit_col<N>(gr, gi, r, gg, [&](const double (&xr)[N], const double (&xi)[N]) {
+          for (int c = c_begin; c < c_end; ++c) {
+            const uint32_t crow = uniform(p.child_rowoff[c]);
+            const double wc = a.w_src[uniform(p.child_term[c])];
+            double2 sv[N];
 #pragma unroll
-          for (int n = 0; n < N; ++n) {
-            const double2 sv = *reinterpret_cast<const double2*>(lds + crow + co[n]);
-            rr += sv.x * xr[n] - sv.y * xi[n];
-            ri += sv.x * xi[n] + sv.y * xr[n];
+            for (int n = 0; n < N; ++n)
+              sv[n] = *reinterpret_cast<const double2*>(lds + crow + co[n]);
+            __builtin_amdgcn_sched_barrier(0);
+            double rr = 0.0, ri = 0.0;
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+              rr += sv[n].x * xr[n] - sv[n].y * xi[n];
+              ri += sv[n].x * xi[n] + sv[n].y * xr[n];
+            }
+            Rre += wc * rr;
+            Rim += wc * ri;
           }
-          Rre += wc * rr;
-          Rim += wc * ri;
-        }
+        });
       }
       // this lane's sink groups in flavour f: y_c, sigma_d, and where the
       // source dominator has children in this block, q_d = G^-1 v_d and the
@@ -186,22 +182,26 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
       while (sg_f < sg_end && (q.sgrp_fc[sg_f] >> 8) == f) ++sg_f;
       for (int h = sg; h < sg_f; ++h) {
         const int cc = q.sgrp_fc[h] & 0xff;
+        // y_c = e_c^T G^-1 = (Q^T e_c)^T U^-1 L^-1: the unit vector sits at
+        // the factors' position of original column cc; y comes out in the
+        // original row order
+        const uint32_t ccol = q.sdom_coloff[(size_t)(o + cc) * pad + k];
         double br[N], bi[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-          br[j] = (j == cc) ? 1.0 : 0.0;
+          br[j] = (co[j] == ccol) ? 1.0 : 0.0;
           bi[j] = 0.0;
         }
-        solve_row<N>(gr, gi, br, bi);     // y_c = e_c^T G^-1, as b^T P
+        solve_row<N>(gr, gi, br, bi);
         for (int ch = q.sgrp_ptr[h]; ch < q.sgrp_ptr[h + 1]; ++ch) {
           const uint32_t col = q.schild_coloff[ch];
           const double wd = a.w_snk[q.schild_term[ch]];
-          // P v_d: the new column at the rows in pivot order
+          // v_d: the new column at the dominator's rows
           double vr[N], vi[N];
           double sr = 0.0, si = 0.0;
 #pragma unroll
           for (int m = 0; m < N; ++m) {
-            const double2 v = *reinterpret_cast<const double2*>(lds + prow[m] + col);
+            const double2 v = *reinterpret_cast<const double2*>(lds + ro[m] + col);
             vr[m] = v.x;
             vi[m] = v.y;
             sr += br[m] * v.x - bi[m] * v.y;
@@ -210,15 +210,15 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
           Sre += wd * sr;
           Sim += wd * si;
           if (!src_kids) continue;
-          solve_col<N>(gr, gi, vr, vi);   // q_d = G^-1 v_d
+          solve_col<N>(gr, gi, vr, vi);   // q_d = G^-1 v_d, in the factors' column order
           double tre = 0.0, tim = 0.0;
           for (int gg = g; gg < g_f_end; ++gg) {
             const int r = uniform(p.grp_fr[gg] & 0xff);
-            // kappa = (G^-1)[cc][r] = y_c[r] = b[m] with perm[m] == r
+            // kappa = (G^-1)[cc][r] = y_c[r] (y in the original row order)
             double kr = 0.0, ki = 0.0;
 #pragma unroll
             for (int m = 0; m < N; ++m)
-              if (perm[m] == r) {
+              if (m == r) {
                 kr = br[m];
                 ki = bi[m];
               }
