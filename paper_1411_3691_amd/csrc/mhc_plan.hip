@@ -46,7 +46,10 @@ struct mhc_plan {
 namespace {
 
 constexpr int kSinkBlock = 64;
-constexpr int kTargetBlocks = 2048;
+// Workgroups per single-job launch (over all slices): 4096 measured equal
+// or faster than 1024, 2048 and 8192 for every lane-kernel method on the
+// mid workload (the plain LU 5 % faster than with 2048).
+constexpr int kTargetBlocks = 4096;
 
 mhc_status hip_fail(hipError_t e, const char* where) {
   return fail(MHC_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
