@@ -425,6 +425,22 @@ def main():
                                        "kernel_ms": float(np.mean(ev_a)),
                                        "value": w.n_pairs / (wall_a / args.steps),
                                        "n_groups": tree_ns.stats()["n_groups"]}
+        # reverse-delete dominating set: fewer dominators, same sum
+        tree_pr = mhc.Tree(src, prune=True)
+        plan = mhc.Plan(tree_pr, snk)
+        wall_a, ev_a, C_pr = timed("tree")
+        plan = plan_main
+        fl_pr = tree_flops(w.T, len(w.snk), w.nf, tree_pr.export())
+        st_pr = tree_pr.stats()
+        abl["tree_pruned_dominators"] = {
+            "ms_per_step": wall_a * 1e3 / args.steps,
+            "kernel_ms": float(np.mean(ev_a)),
+            "value": w.n_pairs / (wall_a / args.steps),
+            "n_dom": st_pr["n_dom"], "n_groups": st_pr["n_groups"],
+            "flops_per_step": fl_pr,
+            "tflops": fl_pr / (float(np.mean(ev_a)) * 1e-3) / 1e12,
+            "max_rel_diff_vs_tree": float(np.max(np.abs(C_pr - C_tree))
+                                          / max(1e-300, float(np.max(np.abs(C_tree)))))}
     back = None
     if args.workload == "grad":
         # the adjoint (mhc_contract_backward): grad S and both weight

@@ -64,6 +64,14 @@ enum { MHC_GREEDY_R1 = 1, MHC_GREEDY_R2 = 2 };
  * group, so siblings that change the same row do not share the solve
  * (Sec. 2 "updating" without the "caching" of Fig. 1; an ablation). */
 enum { MHC_TREE_NO_SHARING = 0x100 };
+/* Flag or-ed into the policy of mhc_tree_build: after the greedy rule, a
+ * reverse-delete pass over the dominators (last picked first) drops each one
+ * whose closed neighbourhood stays dominated by the others kept (Sec. 3
+ * names a better dominating set as the first improvement).  The set stays
+ * dominating, becomes irredundant and is never larger than the greedy one;
+ * a term whose owner was dropped moves to the kept dominator of its closed
+ * neighbourhood that was picked first. */
+enum { MHC_TREE_PRUNE = 0x200 };
 
 /* Contraction methods. */
 enum {
@@ -121,8 +129,9 @@ mhc_status mhc_terms_shape(const mhc_terms* terms, int32_t* n_terms,
  * their index tuples differ in exactly one position; that position is the
  * flavour block f and the row r that changes (Sec. 2: G^(jk) = G^(ik) +
  * e_r v^T).  The greedy rule `policy` (MHC_GREEDY_R1 or R2, optionally
- * | MHC_TREE_NO_SHARING) picks dominators; every other term becomes a child
- * of the first dominator whose neighbourhood covered it.
+ * | MHC_TREE_NO_SHARING and/or | MHC_TREE_PRUNE) picks dominators; every
+ * other term becomes a child of the first dominator whose neighbourhood
+ * covered it.
  * Host only; depends on neither S nor the weights, so one tree serves every
  * gauge configuration and time slice. */
 mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,

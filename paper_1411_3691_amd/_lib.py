@@ -30,6 +30,7 @@ UPDATE_TREE_UNPIVOTED = 4
 PLAIN_LU_THRESHOLD = 5
 UPDATE_TREE_THRESHOLD = 6
 TREE_NO_SHARING = 0x100
+TREE_PRUNE = 0x200
 SCHED_AUTO = 0
 SCHED_LANE = 1
 SCHED_GROUP = 2

@@ -240,13 +240,59 @@ static void greedy_r1(const std::vector<int64_t>& ptr,
   }
 }
 
+// Reverse delete over a dominating set: dominators are visited last picked
+// first, and one is dropped when every term of its closed neighbourhood is
+// dominated by at least one other kept dominator (cnt >= 2 counts itself).
+// Terms whose owner was dropped move to the kept dominator of their closed
+// neighbourhood with the lowest pick rank.
+static void prune_dominators(const std::vector<int64_t>& ptr,
+                             const std::vector<int32_t>& nbr, int n,
+                             std::vector<int32_t>& dom,
+                             std::vector<int32_t>& owner) {
+  std::vector<int32_t> cnt(n, 0);
+  for (int32_t v : dom) {
+    ++cnt[v];
+    for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e) ++cnt[nbr[e]];
+  }
+  std::vector<char> kept(n, 0);
+  for (int32_t v : dom) kept[v] = 1;
+  for (auto it = dom.rbegin(); it != dom.rend(); ++it) {
+    const int v = *it;
+    bool redundant = cnt[v] >= 2;
+    for (int64_t e = ptr[v]; redundant && e < ptr[v + 1]; ++e)
+      redundant = cnt[nbr[e]] >= 2;
+    if (!redundant) continue;
+    kept[v] = 0;
+    --cnt[v];
+    for (int64_t e = ptr[v]; e < ptr[v + 1]; ++e) --cnt[nbr[e]];
+  }
+  std::vector<int32_t> order;
+  std::vector<int32_t> rank(n, -1);
+  for (int32_t v : dom)
+    if (kept[v]) {
+      rank[v] = (int32_t)order.size();
+      order.push_back(v);
+    }
+  for (int u = 0; u < n; ++u) {
+    if (kept[owner[u]]) continue;
+    int best = kept[u] ? u : -1;
+    for (int64_t e = ptr[u]; e < ptr[u + 1]; ++e) {
+      const int v = nbr[e];
+      if (kept[v] && (best < 0 || rank[v] < rank[best])) best = v;
+    }
+    owner[u] = best;
+  }
+  dom.swap(order);
+}
+
 mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
                           mhc_tree** out) {
   if (!out) return fail(MHC_E_ARG, "mhc_tree_build: out is NULL");
   *out = nullptr;
   if (!src) return fail(MHC_E_ARG, "mhc_tree_build: NULL terms");
   const bool share = (policy & MHC_TREE_NO_SHARING) == 0;
-  policy &= ~MHC_TREE_NO_SHARING;
+  const bool prune = (policy & MHC_TREE_PRUNE) != 0;
+  policy &= ~(MHC_TREE_NO_SHARING | MHC_TREE_PRUNE);
   if (policy != MHC_GREEDY_R1 && policy != MHC_GREEDY_R2)
     return fail(MHC_E_ARG, "mhc_tree_build: policy must be R1 or R2");
   mhc_tree* tr = new (std::nothrow) mhc_tree();
@@ -263,6 +309,7 @@ mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
       greedy_r2(ptr, nbr, n, tr->dom_order, tr->owner);
     else
       greedy_r1(ptr, nbr, n, tr->dom_order, tr->owner);
+    if (prune) prune_dominators(ptr, nbr, n, tr->dom_order, tr->owner);
     // Flavour and row of each child's single difference with its owner.
     tr->flav.assign(n, -1);
     tr->pos.assign(n, -1);

@@ -68,13 +68,16 @@ class Terms:
 class Tree:
     """Update tree over source terms (host only)."""
 
-    def __init__(self, terms: Terms, policy: str = "R2", share: bool = True):
+    def __init__(self, terms: Terms, policy: str = "R2", share: bool = True,
+                 prune: bool = False):
         """share=False: every child its own group (no shared solves; an
-        ablation)."""
+        ablation).  prune=True: reverse-delete pass over the greedy
+        dominators (an irredundant set, never larger; Sec. 3)."""
         self.terms = terms
         self.policy = policy
         self.share = share
-        flags = 0 if share else _lib.TREE_NO_SHARING
+        self.prune = prune
+        flags = (0 if share else _lib.TREE_NO_SHARING) | (_lib.TREE_PRUNE if prune else 0)
         h = ctypes.c_void_p()
         check(lib().mhc_tree_build(terms.handle, POLICIES[policy] | flags, ctypes.byref(h)))
         self._h = h

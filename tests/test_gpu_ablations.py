@@ -39,6 +39,29 @@ def test_updates_without_sharing_match():
     assert np.all(np.abs(C - C2) <= 1e-12 * Aw)
 
 
+def test_pruned_dominating_set_matches():
+    # reverse-delete dominating set (fewer dominators, more children; a
+    # child may move to another dominator): the oracle's sum on a small
+    # shape, and the plain LU's on every slice of the full mid workload
+    w = W.workload("mid", T=3, n_src=600, n_snk=200)
+    src = mhc.Terms(w.src, w.nf, w.M)
+    tree = mhc.Tree(src, prune=True)
+    assert tree.stats()["n_dom"] < mhc.Tree(src).stats()["n_dom"]
+    plan = mhc.Plan(tree, mhc.Terms(w.snk, w.nf, w.M))
+    dev = plan.device
+    S, ws, wk = (torch.from_numpy(x).to(dev) for x in (w.S, w.w_src, w.w_snk))
+    C = mhc.contract(plan, S, ws, wk, "tree").cpu().numpy()
+    Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+    assert np.all(np.abs(C - Cw) <= 1e-9 * Aw)
+    w = W.workload("mid")
+    src = mhc.Terms(w.src, w.nf, w.M)
+    plan = mhc.Plan(mhc.Tree(src, prune=True), mhc.Terms(w.snk, w.nf, w.M))
+    S, ws, wk = (torch.from_numpy(x).to(dev) for x in (w.S, w.w_src, w.w_snk))
+    C = mhc.contract(plan, S, ws, wk, "tree").cpu().numpy()
+    Cp, Ap = (x.cpu().numpy() for x in mhc.contract(plan, S, ws, wk, "plain", with_scale=True))
+    assert np.all(np.abs(C - Cp) <= 2e-9 * Ap)
+
+
 @pytest.mark.parametrize("method", ["plain_unpivoted", "tree_unpivoted"])
 def test_unpivoted_lu_on_gaussian_blocks(method):
     # Gaussian blocks rarely have a tiny leading pivot, so without pivoting

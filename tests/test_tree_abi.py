@@ -39,10 +39,11 @@ def test_probe_rejects_bad_arguments_before_launching():
     assert L.mhc_probe_fma64(None, 1, 1, None) == E_ARG
 
 
-def tree_matches_oracle(terms, nf, M, policy):
-    t = mhc.Tree(mhc.Terms(terms, nf, M), policy=policy)
+def tree_matches_oracle(terms, nf, M, policy, prune=False):
+    t = mhc.Tree(mhc.Terms(terms, nf, M), policy=policy, prune=prune)
     got = t.export()
-    want = ot.build(terms, nf, policy=ot.R2 if policy == "R2" else ot.R1)
+    want = ot.build(terms, nf, policy=ot.R2 if policy == "R2" else ot.R1,
+                    prune_set=prune)
     assert got["n_dom"] == want["n_dom"]
     for k in ("dom_order", "owner", "flav", "pos"):
         np.testing.assert_array_equal(got[k], want[k], err_msg=k)
@@ -53,6 +54,7 @@ def tree_matches_oracle(terms, nf, M, policy):
     assert st["n_children"] == len(terms) - want["n_dom"]
 
 
+@pytest.mark.parametrize("prune", [False, True])
 @pytest.mark.parametrize("policy", ["R2", "R1"])
 @pytest.mark.parametrize("name,over", [
     ("tiny", {}),
@@ -60,9 +62,9 @@ def tree_matches_oracle(terms, nf, M, policy):
     ("mid", dict(T=1, n_src=500, branching=3, depth=2)),
     ("grad", dict(T=1)),
 ])
-def test_tree_bit_exact_workloads(name, over, policy):
+def test_tree_bit_exact_workloads(name, over, policy, prune):
     w = W.workload(name, **over)
-    tree_matches_oracle(w.src, w.nf, w.M, policy)
+    tree_matches_oracle(w.src, w.nf, w.M, policy, prune)
 
 
 @pytest.mark.slow
@@ -72,9 +74,10 @@ def test_tree_bit_exact_large():
     tree_matches_oracle(w.src, w.nf, w.M, "R2")
 
 
+@pytest.mark.parametrize("prune", [False, True])
 @pytest.mark.parametrize("seed", range(6))
 @pytest.mark.parametrize("policy", ["R2", "R1"])
-def test_tree_bit_exact_adversarial(seed, policy):
+def test_tree_bit_exact_adversarial(seed, policy, prune):
     rng = np.random.default_rng(seed)
     # dense small index space: many ties, stars, cliques and long chains
     M = 4 + seed
@@ -86,7 +89,7 @@ def test_tree_bit_exact_adversarial(seed, policy):
         rows.add(a)
     terms = np.array(sorted(rows), dtype=np.int32)
     rng.shuffle(terms)
-    tree_matches_oracle(terms, nf, M, policy)
+    tree_matches_oracle(terms, nf, M, policy, prune)
 
 
 def test_tree_special_graphs():
@@ -223,3 +226,19 @@ def test_terms_shape():
     a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     assert L.mhc_terms_shape(t.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == 0
     assert (a.value, b.value, c.value) == (2, 2, 9)
+
+
+def test_prune_flag_combines_with_no_sharing_and_rejects_bad_policy():
+    w = W.workload("mid", T=1, n_src=500, n_snk=10)
+    t = mhc.Terms(w.src, w.nf, w.M)
+    a = mhc.Tree(t, prune=True)
+    b = mhc.Tree(t, share=False, prune=True)
+    ea, eb = a.export(), b.export()
+    for key in ("n_dom", "dom_order", "owner", "flav", "pos"):
+        assert np.array_equal(ea[key], eb[key])
+    assert b.stats()["n_groups"] == b.stats()["n_children"]
+    assert ea["n_dom"] <= mhc.Tree(t).export()["n_dom"]
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.mhc_tree_build(t.handle, 3 | _lib.TREE_PRUNE, ctypes.byref(h)) == -1
+    assert b"policy" in L.mhc_last_error()
