@@ -11,10 +11,10 @@ from paper_1411_3691_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def setup(w):
+def setup(w, prune=False):
     src = mhc.Terms(w.src, w.nf, w.M)
     snk = mhc.Terms(w.snk, w.nf, w.M)
-    plan = mhc.Plan(mhc.Tree(src), snk)
+    plan = mhc.Plan(mhc.Tree(src, prune=prune), snk)
     dev = plan.device
     return (plan, torch.from_numpy(w.S).to(dev), torch.from_numpy(w.w_src).to(dev),
             torch.from_numpy(w.w_snk).to(dev))
@@ -129,10 +129,12 @@ def test_backward_repeatable_in_weights(method):
                                atol=1e-14 * float(a[0].abs().max()))
 
 
-def test_tree_backward_matches_plain_backward():
-    # 3 slices, mid blocks, 400 x 150 tree terms (several sink blocks)
+@pytest.mark.parametrize("prune", [False, True])
+def test_tree_backward_matches_plain_backward(prune):
+    # 3 slices, mid blocks, 400 x 150 tree terms (several sink blocks); also
+    # on the reverse-delete dominating set (children moved between dominators)
     w = W.workload("mid", T=3, n_src=400, n_snk=150)
-    plan, S, ws, wk = setup(w)
+    plan, S, ws, wk = setup(w, prune)
     g = torch.tensor([0.5 + 1j, -1.0 + 0.25j, 2.0 - 1j], dtype=torch.complex128)
     p = [x.cpu().numpy() for x in mhc.contract_backward(plan, S, ws, wk, g, "plain")]
     t = [x.cpu().numpy() for x in mhc.contract_backward(plan, S, ws, wk, g, "tree")]

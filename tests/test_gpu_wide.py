@@ -12,8 +12,9 @@ from parity_util import all_pairs, check_C, check_pairs
 pytestmark = pytest.mark.gpu
 
 
-def setup(w, policy="R2"):
-    plan = mhc.Plan(mhc.Tree(mhc.Terms(w.src, w.nf, w.M), policy), mhc.Terms(w.snk, w.nf, w.M))
+def setup(w, policy="R2", prune=False):
+    plan = mhc.Plan(mhc.Tree(mhc.Terms(w.src, w.nf, w.M), policy, prune=prune),
+                    mhc.Terms(w.snk, w.nf, w.M))
     dev = plan.device
     return (plan, torch.from_numpy(w.S).to(dev), torch.from_numpy(w.w_src).to(dev),
             torch.from_numpy(w.w_snk).to(dev))
@@ -43,6 +44,22 @@ def test_wide_blocks_all_pairs(nf, M, n_src, n_snk):
         C, A, P = run(plan, S, ws, wk, method)
         check_pairs(w, P, *all_pairs(w))
         check_C(C, A, Cw, Aw)
+
+
+@pytest.mark.parametrize("nf,M,n_src,n_snk", [
+    ((3, 5), 20, 120, 37),
+    ((12, 12), 40, 150, 19),
+    ((9, 17), 40, 60, 15),
+])
+def test_wide_blocks_pruned_dominating_set(nf, M, n_src, n_snk):
+    # reverse-delete dominators (fewer LUs, children moved to other
+    # dominators) through the group kernels: every pair det and C
+    w = W.workload("mid", T=2, M=M, nf=nf, n_src=n_src, n_snk=n_snk, branching=4, depth=3)
+    plan, S, ws, wk = setup(w, prune=True)
+    Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+    C, A, P = run(plan, S, ws, wk, "tree")
+    check_pairs(w, P, *all_pairs(w))
+    check_C(C, A, Cw, Aw)
 
 
 @pytest.mark.parametrize("nf,n_src,n_snk", [
