@@ -425,7 +425,10 @@ def main():
                                        "kernel_ms": float(np.mean(ev_a)),
                                        "value": w.n_pairs / (wall_a / args.steps),
                                        "n_groups": tree_ns.stats()["n_groups"]}
+    if args.workload in ("mid", "large"):
         # reverse-delete dominating set: fewer dominators, same sum
+        abl = abl if abl is not None else {}
+        plan_main = plan
         tree_pr = mhc.Tree(src, prune=True)
         plan = mhc.Plan(tree_pr, snk)
         wall_a, ev_a, C_pr = timed("tree")
