@@ -484,6 +484,25 @@ def main():
                "max_rel_diff_vs_plain": float(np.max(np.abs(C_two - C_plain)) /
                                               max(1e-300, float(np.max(np.abs(C_plain))))),
                "sink_tree": {**stree.stats(), "build_s": t_stree}}
+        # both trees on reverse-delete dominating sets: fewer (source
+        # dominator, sink dominator) LUs
+        tree_p2, stree_p2 = mhc.Tree(src, prune=True), mhc.Tree(snk, prune=True)
+        plan_p2 = mhc.Plan(tree_p2, snk)
+        plan_p2.attach_sink_tree(stree_p2)
+        plan_main = plan
+        plan = plan_p2
+        wall_p2, ev_p2, C_p2 = timed("tree2")
+        plan = plan_main
+        fl_p2 = two_sided_flops(w.T, w.nf, tree_p2.export(), stree_p2.export())
+        two["pruned_dominators"] = {
+            "value": w.n_pairs / (wall_p2 / args.steps),
+            "ms_per_step": wall_p2 * 1e3 / args.steps,
+            "kernel_ms": float(np.mean(ev_p2)),
+            "n_dom_src": tree_p2.stats()["n_dom"], "n_dom_snk": stree_p2.stats()["n_dom"],
+            "flops_per_step": fl_p2,
+            "tflops": fl_p2 / (float(np.mean(ev_p2)) * 1e-3) / 1e12,
+            "max_rel_diff_vs_plain": float(np.max(np.abs(C_p2 - C_plain)) /
+                                           max(1e-300, float(np.max(np.abs(C_plain)))))}
     pairs = w.n_pairs
     ms_tree = wall_tree * 1e3 / args.steps
     ms_plain = wall_plain * 1e3 / args.steps

@@ -15,11 +15,11 @@ from parity_util import check_pairs
 pytestmark = pytest.mark.gpu
 
 
-def setup(w, policy="R2"):
+def setup(w, policy="R2", prune=False):
     src = mhc.Terms(w.src, w.nf, w.M)
     snk = mhc.Terms(w.snk, w.nf, w.M)
-    tree = mhc.Tree(src, policy)
-    stree = mhc.Tree(snk, policy)
+    tree = mhc.Tree(src, policy, prune=prune)
+    stree = mhc.Tree(snk, policy, prune=prune)
     plan = mhc.Plan(tree, snk)
     plan.attach_sink_tree(stree)
     dev = plan.device
@@ -31,6 +31,16 @@ def c_tree2(plan, S, ws, wk):
     C = mhc.contract(plan, S, ws, wk, "tree2")
     torch.cuda.synchronize()
     return C.cpu().numpy()
+
+
+@pytest.mark.parametrize("prune", [False, True])
+def test_pruned_trees_against_oracle(prune):
+    # both trees on reverse-delete dominating sets, mid blocks, every slice
+    w = W.workload("mid", T=2, n_src=300, n_snk=200)
+    plan, tree, stree, S, ws, wk = setup(w, prune=prune)
+    C = c_tree2(plan, S, ws, wk)
+    Cw, Aw = oc.correlator(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk)
+    assert np.all(np.abs(C - Cw) <= 1e-9 * Aw)
 
 
 @pytest.mark.parametrize("nf,M,n_src,n_snk,b,depth", [
@@ -97,11 +107,13 @@ def test_single_pairs_of_every_kind():
     check_pairs(w, P, np.array(ts), np.array(is_), np.array(js))
 
 
-def test_agrees_with_one_sided_and_plain_at_mid_size():
+@pytest.mark.parametrize("prune", [False, True])
+def test_agrees_with_one_sided_and_plain_at_mid_size(prune):
     # 32 slices, M = 48, blocks of 6, 2000 x 2000 tree terms (the mid
-    # workload itself)
+    # workload itself); also with both trees on reverse-delete dominating
+    # sets
     w = W.workload("mid")
-    plan, tree, stree, S, ws, wk = setup(w)
+    plan, tree, stree, S, ws, wk = setup(w, prune=prune)
     Cp, Ap = mhc.contract(plan, S, ws, wk, "plain", with_scale=True)
     Ct = mhc.contract(plan, S, ws, wk, "tree")
     C2 = mhc.contract(plan, S, ws, wk, "tree2")
