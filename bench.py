@@ -277,6 +277,25 @@ def bench_batch(args):
     wall_plain, ev_plain, C_plain, _ = timed("plain")
     rel = max(float(np.max(np.abs(x - y)) / max(1e-300, float(np.max(np.abs(y)))))
               for x, y in zip(C_tree, C_plain))
+    # every job's tree on its reverse-delete dominating set
+    plans_main, plans = plans, []
+    fl_pr, n_dom_g, n_dom_p = 0.0, 0, 0
+    for w, pm in zip(ws, plans_main):
+        terms = mhc.Terms(w.src, w.nf, w.M)
+        tree = mhc.Tree(terms, prune=True)
+        plans.append(mhc.Plan(tree, mhc.Terms(w.snk, w.nf, w.M)))
+        fl_pr += tree_flops(w.T, len(w.snk), w.nf, tree.export())
+        n_dom_p += tree.stats()["n_dom"]
+        n_dom_g += mhc.Tree(terms).stats()["n_dom"]
+    wall_pr, ev_pr, C_pr, _ = timed("tree")
+    plans = plans_main
+    pruned = {"value": pairs / (wall_pr / args.steps),
+              "ms_per_step": wall_pr * 1e3 / args.steps, "kernel_ms": ev_pr,
+              "n_dom": n_dom_p, "n_dom_greedy": n_dom_g, "flops_per_step": fl_pr,
+              "tflops": fl_pr / (ev_pr * 1e-3) / 1e12,
+              "max_rel_diff_vs_plain": max(
+                  float(np.max(np.abs(x - y)) / max(1e-300, float(np.max(np.abs(y)))))
+                  for x, y in zip(C_pr, C_plain))}
     ach = fl_tree / (ev_tree * 1e-3) / 1e12
     nfs = sorted({n for w in ws for n in w.nf})
     out = {
@@ -305,6 +324,7 @@ def bench_batch(args):
         "speedup_vs_plain": wall_plain / wall_tree,
         "tree_vs_plain_max_rel_diff": rel,
         "tree": {"kernel_ms": ev_tree, "flops_per_step": fl_tree, "plan_s": t_plan, **info},
+        "tree_pruned_dominators": pruned,
         "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None},
         "cpu_baseline": cpu,
