@@ -121,7 +121,9 @@ mhc_status mhc_terms_create(int32_t n_terms, int32_t n_flavors,
                             const int32_t* n_per_flavor, const int32_t* idx,
                             int32_t M, mhc_terms** out);
 void mhc_terms_destroy(mhc_terms* terms);
-/* Shape queries (any pointer may be NULL). */
+/* Shape of a term set (any pointer may be NULL): number of terms, number
+ * of flavour blocks and the size M of the quark index space (Sec. 1: a term
+ * is one product of quark operators per flavour, indices in [0, M)). */
 mhc_status mhc_terms_shape(const mhc_terms* terms, int32_t* n_terms,
                            int32_t* n_flavors, int32_t* M);
 
@@ -136,7 +138,9 @@ mhc_status mhc_terms_shape(const mhc_terms* terms, int32_t* n_terms,
  * gauge configuration and time slice. */
 mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
                           mhc_tree** out);
-/* Copy the tree out (host arrays of n_terms int32 each, any may be NULL):
+/* Copy the tree out (Sec. 3: the greedy dominating set and the dominator
+ * each other term hangs off; Sec. 2: the row in which it differs).  Host
+ * arrays of n_terms int32 each, any may be NULL:
  *   n_dom            number of dominators
  *   dom_order[k]     k-th dominator chosen (k < n_dom), -1 after that
  *   owner[u]         dominator owning term u (owner[d] == d for dominators)
@@ -145,9 +149,30 @@ mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
 mhc_status mhc_tree_export(const mhc_tree* tree, int32_t* n_dom,
                            int32_t* dom_order, int32_t* owner, int32_t* flav,
                            int32_t* pos);
-/* Counts: dominators, (dominator, flavour, row) groups, children. */
+/* Counts of the tree (any pointer may be NULL): dominators (Sec. 3: the
+ * matrices that get a full factorisation), (dominator, flavour, row)
+ * groups (Sec. 2: children that change the same row of a dominator share
+ * one solve) and children (every other term). */
 mhc_status mhc_tree_stats(const mhc_tree* tree, int32_t* n_dom,
                           int32_t* n_groups, int32_t* n_children);
+/* Copy out the group tables the kernels read (host arrays, caller-owned,
+ * sized by mhc_tree_stats; any pointer may be NULL).  Sec. 2: children of a
+ * dominator that change the same row r of flavour block f share the solve
+ * x = G_f^-1 e_r; Sec. 3: dominators are processed in the order the greedy
+ * rule picked them.
+ *   dom_grp    [n_dom + 1]   groups of the k-th dominator (dom_order[k]) are
+ *                            dom_grp[k] .. dom_grp[k+1]-1
+ *   grp_f      [n_groups]    flavour block of each group
+ *   grp_r      [n_groups]    changed row of each group
+ *   grp_ptr    [n_groups+1]  children of group g are
+ *                            grp_child[grp_ptr[g] .. grp_ptr[g+1]-1]
+ *   grp_child  [n_children]  term indices
+ * Within a dominator groups are sorted by (f, r) ascending; within a group
+ * children are in ascending term order.  With MHC_TREE_NO_SHARING every
+ * child is a group of its own (same order).
+ * Errors: MHC_E_ARG (NULL tree). */
+mhc_status mhc_tree_groups(const mhc_tree* tree, int32_t* dom_grp, int32_t* grp_f,
+                           int32_t* grp_r, int32_t* grp_ptr, int32_t* grp_child);
 void mhc_tree_destroy(mhc_tree* tree);
 
 /* Device plan: the source tree and the sink terms uploaded once to the

@@ -59,6 +59,7 @@ SIGNATURES = {
     "mhc_tree_build": (_I32, [_P, _I32, ctypes.POINTER(_P)]),
     "mhc_tree_export": (_I32, [_P, _PI32, _PI32, _PI32, _PI32, _PI32]),
     "mhc_tree_stats": (_I32, [_P, _PI32, _PI32, _PI32]),
+    "mhc_tree_groups": (_I32, [_P, _PI32, _PI32, _PI32, _PI32, _PI32]),
     "mhc_tree_destroy": (None, [_P]),
     "mhc_plan_create": (_I32, [_P, _P, _P, ctypes.POINTER(_P)]),
     "mhc_plan_destroy": (None, [_P]),

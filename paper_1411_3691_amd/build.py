@@ -31,8 +31,20 @@ SOURCES = ["mhc_host.cpp", "mhc_plan.hip", "contract_kernels.hip", "wide_kernels
            "adjoint_kernels.hip", "tree2_kernels.hip", "probe_kernels.hip"]
 
 
-def _compile(src: str) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """True when obj is missing or older than src or any header."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [
+        os.path.join(d, h) for d in (CSRC, INCLUDE) for h in os.listdir(d) if h.endswith(".h")]
+    return any(os.path.getmtime(x) > t for x in deps)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and not _stale(src, obj):
+        return obj
     cmd = [HIPCC, *COMMON]
     if src.endswith(".hip"):
         cmd += ["-x", "hip"]
@@ -43,11 +55,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles every source and links libmhc.so; returns its path."""
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compiles every source (with incremental=True only those newer than
+    their objects or older than a header) and links libmhc.so; returns its
+    path."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -60,5 +74,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -387,6 +387,20 @@ mhc_status mhc_tree_export(const mhc_tree* tr, int32_t* n_dom,
   return MHC_OK;
 }
 
+mhc_status mhc_tree_groups(const mhc_tree* tr, int32_t* dom_grp, int32_t* grp_f,
+                           int32_t* grp_r, int32_t* grp_ptr, int32_t* grp_child) {
+  if (!tr) return fail(MHC_E_ARG, "mhc_tree_groups: NULL tree");
+  auto put = [](int32_t* dst, const std::vector<int32_t>& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(int32_t));
+  };
+  put(dom_grp, tr->dom_grp);
+  put(grp_f, tr->grp_f);
+  put(grp_r, tr->grp_r);
+  put(grp_ptr, tr->grp_ptr);
+  put(grp_child, tr->grp_child);
+  return MHC_OK;
+}
+
 mhc_status mhc_tree_stats(const mhc_tree* tr, int32_t* n_dom,
                           int32_t* n_groups, int32_t* n_children) {
   if (!tr) return fail(MHC_E_ARG, "mhc_tree_stats: NULL tree");

@@ -97,6 +97,20 @@ class Tree:
         arrs["n_dom"] = int(n_dom.value)
         return arrs
 
+    def groups(self) -> dict:
+        """The group tables the kernels read (mhc_tree_groups): dom_grp,
+        grp_f, grp_r, grp_ptr, grp_child."""
+        st = self.stats()
+        nd, ng, nc = st["n_dom"], st["n_groups"], st["n_children"]
+        out = dict(dom_grp=np.empty(nd + 1, dtype=np.int32),
+                   grp_f=np.empty(ng, dtype=np.int32), grp_r=np.empty(ng, dtype=np.int32),
+                   grp_ptr=np.empty(ng + 1, dtype=np.int32),
+                   grp_child=np.empty(nc, dtype=np.int32))
+        check(lib().mhc_tree_groups(self._h, *(_i32p(out[k]) for k in
+                                               ("dom_grp", "grp_f", "grp_r", "grp_ptr",
+                                                "grp_child"))))
+        return out
+
     def stats(self) -> dict:
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         check(lib().mhc_tree_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))

@@ -285,3 +285,64 @@ def test_prune_near_minimum_on_mid_terms():
     p = ot.build(terms, w.nf, prune_set=True)["n_dom"]
     assert opt <= p <= g
     assert p <= 1.02 * opt and g >= 1.05 * opt
+
+
+# ------------------------------------------------------------ groups
+
+def regroup_by_loops(tree, nf):
+    """Groups of every dominator rebuilt with plain loops: for each dominator
+    in pick order, for every flavour f and row r in ascending order, scan
+    all terms in ascending index and keep the children owned by it that
+    differ in (f, r).  Sec. 2: those children share the solve G_f^-1 e_r."""
+    n = len(tree["owner"])
+    out = []
+    for k in range(tree["n_dom"]):
+        d = int(tree["dom_order"][k])
+        gl = []
+        for f in range(len(nf)):
+            for r in range(nf[f]):
+                kids = []
+                for u in range(n):
+                    if u != d and int(tree["owner"][u]) == d and \
+                            int(tree["flav"][u]) == f and int(tree["pos"][u]) == r:
+                        kids.append(u)
+                if kids:
+                    gl.append(((f, r), kids))
+        out.append((d, gl))
+    return out
+
+
+def test_groups_worked_example():
+    # star of the special-graph test, with a second leaf in row 0 of
+    # flavour 0: the centre (term 3) dominates every leaf; leaves 0 and 5
+    # change the same row (flavour 0, row 0) and share one group, listed in
+    # ascending term order; the groups are ordered by (flavour, row)
+    star = np.array([[5, 1, 2, 3], [0, 6, 2, 3], [0, 1, 7, 3], [0, 1, 2, 3], [0, 1, 2, 8],
+                     [4, 1, 2, 3]])
+    t = ot.build(star, (2, 2))
+    assert ot.groups(t) == [(3, [((0, 0), [0, 5]), ((0, 1), [1]), ((1, 0), [2]),
+                                 ((1, 1), [4])])]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("policy", [ot.R1, ot.R2])
+def test_groups_match_plain_regrouping(seed, policy):
+    # dense index spaces: many same-row siblings, children in every flavour
+    terms = random_terms(seed, n=80, sn=5, M=4)
+    terms = np.unique(terms, axis=0)
+    rng = np.random.default_rng(100 + seed)
+    terms = terms[rng.permutation(len(terms))]
+    nf = (3, 2)
+    for prune in (False, True):
+        t = ot.build(terms, nf, policy=policy, prune_set=prune)
+        assert ot.groups(t) == regroup_by_loops(t, nf)
+        n_groups = sum(len(g) for _, g in ot.groups(t))
+        n_child = sum(len(c) for _, g in ot.groups(t) for _, c in g)
+        assert n_child == len(terms) - t["n_dom"]
+        assert n_groups <= n_child
+
+
+def test_groups_match_plain_regrouping_mid():
+    w = W.workload("mid", T=1, n_src=600)
+    t = ot.build(w.src, w.nf)
+    assert ot.groups(t) == regroup_by_loops(t, w.nf)

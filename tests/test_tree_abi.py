@@ -52,6 +52,32 @@ def tree_matches_oracle(terms, nf, M, policy, prune=False):
     assert st["n_dom"] == want["n_dom"]
     assert st["n_groups"] == sum(len(x[1]) for x in g)
     assert st["n_children"] == len(terms) - want["n_dom"]
+    groups_match_oracle(t.groups(), g)
+
+
+def groups_match_oracle(got, want_groups, share=True):
+    """The library's group tables (what the kernels read) equal the oracle's
+    groups bit for bit: per dominator in pick order, (f, r) ascending,
+    children ascending; without sharing every child is its own group."""
+    dom_grp, gf, gr, gp, gc = (got[k] for k in ("dom_grp", "grp_f", "grp_r", "grp_ptr",
+                                                "grp_child"))
+    assert dom_grp[0] == 0 and gp[0] == 0
+    flat = []
+    for d, gl in want_groups:
+        if share:
+            flat.append(gl)
+        else:
+            flat.append([((f, r), [c]) for (f, r), kids in gl for c in kids])
+    assert len(dom_grp) == len(flat) + 1
+    for k, gl in enumerate(flat):
+        lo, hi = int(dom_grp[k]), int(dom_grp[k + 1])
+        assert hi - lo == len(gl), k
+        for q, ((f, r), kids) in enumerate(gl):
+            g = lo + q
+            assert (int(gf[g]), int(gr[g])) == (f, r), (k, q)
+            assert gc[gp[g]:gp[g + 1]].tolist() == kids, (k, q)
+    assert int(dom_grp[-1]) == len(gf) == len(gr) == len(gp) - 1
+    assert int(gp[-1]) == len(gc)
 
 
 @pytest.mark.parametrize("prune", [False, True])
@@ -67,7 +93,6 @@ def test_tree_bit_exact_workloads(name, over, policy, prune):
     tree_matches_oracle(w.src, w.nf, w.M, policy, prune)
 
 
-@pytest.mark.slow
 def test_tree_bit_exact_large():
     # 20000 source terms of 2 x 12 quarks, 96 quark indices
     w = W.workload("large", T=1)
@@ -242,3 +267,12 @@ def test_prune_flag_combines_with_no_sharing_and_rejects_bad_policy():
     h = ctypes.c_void_p()
     assert L.mhc_tree_build(t.handle, 3 | _lib.TREE_PRUNE, ctypes.byref(h)) == -1
     assert b"policy" in L.mhc_last_error()
+
+
+@pytest.mark.parametrize("name,over", [("tiny", {}), ("mid", dict(T=1))])
+def test_group_tables_without_sharing(name, over):
+    # the ablation's tables: every child its own group, same order
+    w = W.workload(name, **over)
+    t = mhc.Tree(mhc.Terms(w.src, w.nf, w.M), share=False)
+    want = ot.build(w.src, w.nf)
+    groups_match_oracle(t.groups(), ot.groups(want), share=False)
