@@ -186,29 +186,46 @@ mhc_status mhc_plan_create(const mhc_tree* src_tree, const mhc_terms* snk,
                            void* stream, mhc_plan** out);
 void mhc_plan_destroy(mhc_plan* plan);
 
-/* Forward contraction.  Device pointers, caller-owned:
+/* Forward contraction (Sec. 1: C(t) as the weighted double sum of pair
+ * determinants; Secs. 2-3: the update tree).  Device pointers,
+ * caller-owned:
  *   S         complex128 [T][M][M], row = source quark index, column = sink
  *             quark index (Sec. 1)
  *   w_src     double [n_src];  w_snk  double [n_snk]
  *   C         complex128 [T] (output)
  *   A         double [T] or NULL: A(t) = sum_ij |w_i w'_j d_ij(t)| (output;
  *             the scale the result's accuracy is judged against)
- *   pair_det  complex128 [T][n_src][n_snk] or NULL: every d_ij(t) =
- *             prod_f det G_f^(ij)(t) (output; a test hook, at most 4
- *             flavour blocks)
+ *   pair_det  NULL, or a test hook (at most 4 flavour blocks) in one of two
+ *             forms:
+ *             - pairs == NULL: complex128 [T][n_src][n_snk], every
+ *               d_ij(t) = prod_f det G_f^(ij)(t), written by the
+ *               contraction kernels themselves;
+ *             - pairs != NULL: complex128 [n_pairs], d_ij(t) for each
+ *               sampled (t, i, j) = pairs[q][0..2] (device int32
+ *               [n_pairs][3]), evaluated by the method's arithmetic (plain:
+ *               one LU per block; tree: the owner dominator's factorisation,
+ *               the solve of the changed row and the ratio) with the device
+ *               routines of the contraction kernels, after them on the same
+ *               stream; an entry with t, i or j out of range gives NaN.
+ *   n_pairs   0 when pairs is NULL, else in [0, 2^31).
  * T in [1, 65535].  Every method returns the same quantities within
  * floating-point rounding: MHC_PLAIN_LU, MHC_UPDATE_TREE (the paper's
  * method), MHC_UPDATE_TREE2 (needs an attached sink tree, computes neither
  * A nor pair_det: both must be NULL), the unpivoted ablations and the
- * threshold-pivoting variants (blocks of one size n <= 8).  Every pointer must stay valid until the stream has run
- * the work.  The plan holds the workgroup partial sums: two contractions on
- * one plan that overlap in time (on different streams) race; a call that
- * needs a larger partial buffer than any before waits for the device, then
- * grows it. */
+ * threshold-pivoting variants (blocks of one size n <= 8).  Every pointer
+ * must stay valid until the stream has run the work.  The plan holds the
+ * workgroup partial sums: two contractions on one plan that overlap in
+ * time (on different streams) race; a call that needs a larger partial
+ * buffer than any before waits for the device, then grows it.
+ * Errors: MHC_E_ARG (NULL plan or buffer, T or n_pairs out of range, pairs
+ * without pair_det), MHC_E_STATE (MHC_UPDATE_TREE2 without a sink tree),
+ * MHC_E_UNSUPPORTED (method not available for these blocks, pair_det with
+ * more than 4 blocks), MHC_E_DEVICE, MHC_E_OOM. */
 mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
                         const void* S, const double* w_src,
                         const double* w_snk, void* C, double* A,
-                        void* pair_det, void* stream);
+                        void* pair_det, const int32_t* pairs, int64_t n_pairs,
+                        void* stream);
 
 /* Adjoint of mhc_contract (every method computes the same C).  For an
  * incoming gradient gC of a real loss (PyTorch's convention for complex

@@ -28,7 +28,7 @@ COMMON = [
 ]
 
 SOURCES = ["mhc_host.cpp", "mhc_plan.hip", "contract_kernels.hip", "wide_kernels.hip",
-           "adjoint_kernels.hip", "tree2_kernels.hip", "probe_kernels.hip"]
+           "adjoint_kernels.hip", "tree2_kernels.hip", "probe_kernels.hip", "pair_kernels.hip"]
 
 
 def _stale(src: str, obj: str) -> bool:

@@ -22,6 +22,11 @@ struct PlanView {
   const int32_t* child_term;      // [n_children] source term of the child
   // plain method: every source term is its own row set
   const uint32_t* src_rowoff;     // [n_src][sn]
+  // per source term: its dominator's term id (itself for a dominator) and
+  // the (flavour << 8) | row in which it differs from it (-1 for a
+  // dominator); read by the per-pair kernels only
+  const int32_t* term_owner;      // [n_src]
+  const int32_t* term_fr;         // [n_src]
   // sinks, position-major for coalesced loads; padded sinks repeat sink 0
   const uint32_t* snk_coloff;     // [sn][n_snk_pad] byte offset b*16
 };
@@ -65,6 +70,24 @@ struct BatchArgs {
 
 // Flavour blocks supported by the pair-determinant test hook.
 constexpr int kPairFlavors = 4;
+
+// Sampled pair determinants: out[q] = d_ij(t) for (t, i, j) = pairs[q],
+// evaluated by the method's own arithmetic (plain: one LU per block; tree:
+// the owner dominator's factorisation, the shared solve of the changed row
+// and the ratio) with the device routines of the contraction kernels.
+// Entries with t, i or j out of range give NaN.
+struct PairArgs {
+  PlanView plan;
+  const double2* S;               // [T][M][M]
+  const int32_t* pairs;           // [n_pairs][3]
+  double2* out;                   // [n_pairs]
+  int T, n_pairs;
+};
+// n: largest flavour block; narrow: every block of size n <= 8 (one
+// matrix per lane), else one group of lanes per matrix; pivot as for
+// launch_contract (0 none, 1 partial, 2 threshold; narrow only).
+hipError_t launch_pairs(const PairArgs& a, int n, bool narrow, bool tree, int pivot,
+                        hipStream_t s);
 
 // Enqueues the contraction of all T slices with one matrix per lane (every
 // flavour block of size n <= 8) and the final reduction into C[T] (and A[T]

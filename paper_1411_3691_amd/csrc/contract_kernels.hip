@@ -191,7 +191,7 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
               const double wc = a.w_src[cterm];
               sre += wc * rr;
               sim += wc * ri;
-              if (WITH_A && !zero) sabs_reg += fabs(wc) * sqrt(rr * rr + ri * ri);
+              if (WITH_A && !zero) sabs_reg += fabs(wc) * cabs_scaled(rr, ri);
               if (WITH_PAIRS && valid && a.pair_det && !zero) {
                 double cr = rr * dre - ri * dim, ci = rr * dim + ri * dre;
 #pragma unroll
@@ -261,7 +261,7 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
                 fre += wc * cre;
                 fim += wc * cim;
                 const double dr = cre * Xre - cim * Xim, di = cre * Xim + cim * Xre;
-                if (WITH_A) sabs_fb += fabs(wc) * sqrt(dr * dr + di * di);
+                if (WITH_A) sabs_fb += fabs(wc) * cabs_scaled(dr, di);
                 if (WITH_PAIRS && a.pair_det)
                   a.pair_det[((size_t)t * p.n_src + p.child_term[c]) * p.n_snk + k] =
                       make_double2(dr, di);
@@ -297,7 +297,7 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
       if (WITH_A) {
         // |d_child| = |ratio| |P| for children taken by the update; the
         // fallback children carry their own |det| in sabs_fb.
-        const double pabs = sqrt(Pre * Pre + Pim * Pim);
+        const double pabs = cabs_scaled(Pre, Pim);
         acc_a += fabs(wk) * ((fabs(wi) + sabs_reg) * pabs + sabs_fb);
       }
     }

@@ -31,6 +31,17 @@ __device__ __forceinline__ void cinv(double pr, double pi, double mag,
   vi = __builtin_amdgcn_ldexp(-b * r, -e);
 }
 
+// |re + i im|, with both parts scaled by a power of two before squaring so
+// that neither square overflows nor underflows (determinants of decayed
+// propagators reach 1e-260 and below, where re * re is no longer a normal
+// double).  frexp_exp(0) is 0, so a zero argument gives 0.
+__device__ __forceinline__ double cabs_scaled(double re, double im) {
+  const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(re), fabs(im)));
+  const double a = __builtin_amdgcn_ldexp(re, -e);
+  const double b = __builtin_amdgcn_ldexp(im, -e);
+  return __builtin_amdgcn_ldexp(sqrt(a * a + b * b), e);
+}
+
 // The LDS copy of S_t keeps rows of M + 1 complex numbers (one unused):
 // with a stride of M * 16 bytes (a multiple of 128 for M = 12 k) the lanes
 // that read one column of different rows would all hit the same banks.

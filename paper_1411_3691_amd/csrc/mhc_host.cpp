@@ -90,7 +90,7 @@ extern "C" {
 
 const char* mhc_last_error(void) { return mhc::g_last_error.c_str(); }
 
-int32_t mhc_version(void) { return 202; }
+int32_t mhc_version(void) { return 203; }
 
 mhc_status mhc_terms_create(int32_t n_terms, int32_t n_flavors,
                             const int32_t* n_per_flavor, const int32_t* idx,

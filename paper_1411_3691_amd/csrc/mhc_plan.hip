@@ -134,6 +134,9 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
           (uint32_t)src.idx[(size_t)u * sn + src.off[f] + r] * row_bytes;
     }
   }
+  std::vector<int32_t> term_owner(tree->owner), term_fr(src.n_terms, -1);
+  for (int u = 0; u < src.n_terms; ++u)
+    if (tree->owner[u] != u) term_fr[u] = (tree->flav[u] << 8) | tree->pos[u];
   std::vector<uint32_t> src_rowoff((size_t)src.n_terms * sn);
   for (size_t q = 0; q < src_rowoff.size(); ++q)
     src_rowoff[q] = (uint32_t)src.idx[q] * row_bytes;
@@ -155,6 +158,8 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   const size_t o_child_term = append(img, child_term);
   const size_t o_src_rowoff = append(img, src_rowoff);
   const size_t o_snk_coloff = append(img, snk_coloff);
+  const size_t o_term_owner = append(img, term_owner);
+  const size_t o_term_fr = append(img, term_fr);
   const size_t o_fallback = append(img, std::vector<unsigned long long>(2, 0ull));
 
   e = hipMalloc(&pl->dev_tables, img.size());
@@ -191,6 +196,8 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   v.child_term = reinterpret_cast<const int32_t*>(base + o_child_term);
   v.src_rowoff = reinterpret_cast<const uint32_t*>(base + o_src_rowoff);
   v.snk_coloff = reinterpret_cast<const uint32_t*>(base + o_snk_coloff);
+  v.term_owner = reinterpret_cast<const int32_t*>(base + o_term_owner);
+  v.term_fr = reinterpret_cast<const int32_t*>(base + o_term_fr);
   pl->fallback = reinterpret_cast<unsigned long long*>(base + o_fallback);
   pl->singular = pl->fallback + 1;
   *out = pl;
@@ -311,7 +318,8 @@ mhc_status mhc_plan_attach_sink_tree(mhc_plan* pl, const mhc_tree* st, void* str
 
 mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
                         const double* w_src, const double* w_snk, void* C,
-                        double* A, void* pair_det, void* stream) {
+                        double* A, void* pair_det, const int32_t* pairs, int64_t n_pairs,
+                        void* stream) {
   if (!pl) return fail(MHC_E_ARG, "mhc_contract: NULL plan");
   if (!S || !w_src || !w_snk || !C)
     return fail(MHC_E_ARG, "mhc_contract: NULL buffer");
@@ -334,6 +342,13 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
       return fail(MHC_E_UNSUPPORTED,
                   "mhc_contract: the two-sided method computes neither A nor pair dets");
   }
+  if (pairs) {
+    if (!pair_det) return fail(MHC_E_ARG, "mhc_contract: pairs given without pair_det");
+    if (n_pairs < 0 || n_pairs > 0x7fffffffLL)
+      return fail(MHC_E_ARG, "mhc_contract: n_pairs outside [0, 2^31)");
+  } else if (n_pairs != 0) {
+    return fail(MHC_E_ARG, "mhc_contract: n_pairs without pairs");
+  }
   int cur = -1;
   hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e, "mhc_contract/hipGetDevice");
@@ -346,7 +361,10 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   const bool two = method == MHC_UPDATE_TREE2;
   const bool tree = method == MHC_UPDATE_TREE || method == MHC_UPDATE_TREE_UNPIVOTED ||
                     method == MHC_UPDATE_TREE_THRESHOLD;
-  const bool diag = A != nullptr || pair_det != nullptr;
+  // the dense pair table comes from the contraction kernels themselves; a
+  // sampled list from the per-pair kernels after them
+  void* dense_pairs = pairs ? nullptr : pair_det;
+  const bool diag = A != nullptr || dense_pairs != nullptr;
   // one matrix per lane when every block has the same size n <= 8, else one
   // group of lanes per matrix
   const bool narrow = pl->uniform_n && pl->n <= 8;
@@ -383,7 +401,7 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   a.w_src = w_src;
   a.w_snk = w_snk;
   a.partial = pl->partial;
-  a.pair_det = static_cast<double2*>(pair_det);
+  a.pair_det = static_cast<double2*>(dense_pairs);
   a.fallback = pl->fallback;
   a.T = T;
   a.n_items = (int)n_items;
@@ -400,6 +418,18 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
     e = mhc::kern::launch_contract_wide(a, pl->n, tree, diag, static_cast<double2*>(C), A,
                                         reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "mhc_contract/launch");
+  if (pairs && n_pairs > 0) {
+    mhc::kern::PairArgs pa{};
+    pa.plan = pl->view;
+    pa.S = static_cast<const double2*>(S);
+    pa.pairs = pairs;
+    pa.out = static_cast<double2*>(pair_det);
+    pa.T = T;
+    pa.n_pairs = (int)n_pairs;
+    e = mhc::kern::launch_pairs(pa, pl->n, narrow, tree, pivot,
+                                reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mhc_contract/pairs");
+  }
   return MHC_OK;
 }
 

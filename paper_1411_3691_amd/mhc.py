@@ -190,9 +190,12 @@ def _check_dev(x: torch.Tensor, dtype, shape, name, device):
 
 def contract_into(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch.Tensor,
                   C: torch.Tensor, method: str = "tree", A: torch.Tensor | None = None,
-                  pair_det: torch.Tensor | None = None) -> None:
+                  pair_det: torch.Tensor | None = None,
+                  pairs: torch.Tensor | None = None) -> None:
     """Enqueue the contraction on torch's current stream, writing C (and A,
-    pair_det if given).  All tensors live on the plan's device."""
+    pair_det if given).  All tensors live on the plan's device.  pair_det is
+    either every pair determinant [T][n_src][n_snk] (pairs None) or, with
+    pairs an int32 [n][3] tensor of (t, i, j), the sampled ones [n]."""
     T = S.shape[0]
     dev = plan.device
     _check_dev(S, torch.complex128, (T, plan.M, plan.M), "S", dev)
@@ -201,7 +204,14 @@ def contract_into(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch
     _check_dev(C, torch.complex128, (T,), "C", dev)
     if A is not None:
         _check_dev(A, torch.float64, (T,), "A", dev)
-    if pair_det is not None:
+    n_pairs = 0
+    if pairs is not None:
+        if pair_det is None:
+            raise ValueError("pairs needs pair_det")
+        n_pairs = pairs.shape[0]
+        _check_dev(pairs, torch.int32, (n_pairs, 3), "pairs", dev)
+        _check_dev(pair_det, torch.complex128, (n_pairs,), "pair_det", dev)
+    elif pair_det is not None:
         _check_dev(pair_det, torch.complex128, (T, plan.n_src, plan.n_snk), "pair_det", dev)
     check(lib().mhc_contract(
         plan._h, METHODS[method], T, ctypes.c_void_p(S.data_ptr()),
@@ -209,6 +219,7 @@ def contract_into(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch
         ctypes.c_void_p(C.data_ptr()),
         ctypes.c_void_p(A.data_ptr() if A is not None else 0),
         ctypes.c_void_p(pair_det.data_ptr() if pair_det is not None else 0),
+        ctypes.c_void_p(pairs.data_ptr() if pairs is not None else 0), n_pairs,
         _stream_ptr()))
 
 
@@ -231,15 +242,25 @@ def probe_fma64(out: torch.Tensor, iters: int) -> int:
 
 
 def contract(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch.Tensor,
-             method: str = "tree", with_scale: bool = False, with_pairs: bool = False):
+             method: str = "tree", with_scale: bool = False, with_pairs: bool = False,
+             pairs=None):
     """C(t) for every slice (complex128 [T] on the plan's device).  With
-    with_scale / with_pairs also returns A(t) and every pair determinant."""
+    with_scale / with_pairs also returns A(t) and the pair determinants:
+    every one ([T][n_src][n_snk]), or with ``pairs`` (int [n][3] of
+    (t, i, j), any array-like) the sampled ones ([n])."""
     T = S.shape[0]
     C = torch.empty(T, dtype=torch.complex128, device=plan.device)
     A = torch.empty(T, dtype=torch.float64, device=plan.device) if with_scale else None
-    P = (torch.empty((T, plan.n_src, plan.n_snk), dtype=torch.complex128, device=plan.device)
-         if with_pairs else None)
-    contract_into(plan, S, w_src, w_snk, C, method, A, P)
+    pt = None
+    if pairs is not None:
+        with_pairs = True
+        pt = torch.as_tensor(np.ascontiguousarray(np.asarray(pairs, dtype=np.int32)))
+        pt = pt.reshape(-1, 3).to(plan.device).contiguous()
+        P = torch.empty(pt.shape[0], dtype=torch.complex128, device=plan.device)
+    else:
+        P = (torch.empty((T, plan.n_src, plan.n_snk), dtype=torch.complex128,
+                         device=plan.device) if with_pairs else None)
+    contract_into(plan, S, w_src, w_snk, C, method, A, P, pt)
     if not (with_scale or with_pairs):
         return C
     out = [C]

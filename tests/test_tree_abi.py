@@ -179,7 +179,7 @@ def test_null_handles_and_destroy():
     assert L.mhc_tree_export(None, None, None, None, None, None) == -1
     assert L.mhc_tree_stats(None, None, None, None) == -1
     assert L.mhc_plan_create(None, None, None, ctypes.byref(h)) == -1
-    assert L.mhc_contract(None, 1, 1, None, None, None, None, None, None, None) == -1
+    assert L.mhc_contract(None, 1, 1, None, None, None, None, None, None, None, 0, None) == -1
     assert L.mhc_plan_status(None, None, None) == -1
     assert L.mhc_plan_attach_sink_tree(None, None, None) == -1
     assert L.mhc_contract_backward(None, 1, 1, None, None, None, None, None, None, None,
