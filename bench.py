@@ -1,15 +1,21 @@
 """Benchmark: complex128 det-pairs/s of the update-tree contraction against
 the plain batched LU on the same GPU.
 
-    python bench.py [--steps K] [--warmup W] [--workload mid|large|batch]
+    python bench.py [--steps K] [--warmup W] [--workload mid|large|batch|grad]
 
 One step = one update-tree contraction of every (slice, source term, sink
 term) pair of the workload (gather, dominator LU, column solves, sibling
 ratios, weighted reduction: one call of mhc_contract).  Inputs (propagator,
 weights, plan) are resident on the GPU before timing starts.  The plain
 batched LU is timed the same way on the same inputs and reported beside it.
-With ``--workload batch`` a step is one run of the 256-job batch (one graph
-launch of mhc_batch_run over every job).
+
+Without --workload the headline is the mid workload (K timed steps after W
+warm-ups), and the line carries two more measured workloads as
+sub-objects: ``large`` (the full large workload, its own step counts) and
+``batch`` (one graph launch of the 256-job batch per step, with the
+autotuner's cached schedule).  Each sub-object has its own roofline and CPU
+baseline.  Progress goes to stderr, one line per leg.  With --workload the
+line is that workload alone.
 
 Prints one JSON line.  Runs on one GPU only.
 """
@@ -177,6 +183,11 @@ def plain_flops(T, n_src, n_snk, nf) -> float:
     return float(T) * n_src * n_snk * (sum(f_lu(n) for n in nf) + 11)
 
 
+def log(msg: str) -> None:
+    """One progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(w, target_s: float = 15.0):
     """The CPU oracle on a bounded sample of the same workload: the first
     slices (or, below one slice, the first source terms of slice 0) x all
@@ -205,11 +216,12 @@ def cpu_baseline(w, target_s: float = 15.0):
     dt = time.perf_counter() - t0
     pairs = n_sl * n_rows * len(w.snk)
     return {"value": pairs / dt, "unit": "det-pairs/s", "cores": n_workers, "kind": "oracle",
+            "host_cpu_count": os.cpu_count(),
             "sample": f"slices 0..{n_sl - 1}, source terms 0..{n_rows - 1} x all "
                       f"{len(w.snk)} sink terms ({pairs} pairs, {dt:.1f} s)"}
 
 
-def cpu_baseline_batch(ws, pairs_per_job: int = 200_000):
+def cpu_baseline_batch(ws, pairs_per_job: int = 60_000):
     """The CPU oracle on a fixed 16-job subset of the batch: per job, slice 0
     and the first source terms (about pairs_per_job pairs) x all sink terms."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -224,22 +236,50 @@ def cpu_baseline_batch(ws, pairs_per_job: int = 200_000):
         pairs += rows * len(w.snk)
     dt = time.perf_counter() - t0
     return {"value": pairs / dt, "unit": "det-pairs/s", "cores": n_workers, "kind": "oracle",
+            "host_cpu_count": os.cpu_count(),
             "sample": f"jobs 0..15 of the batch, slice 0, about {pairs_per_job} pairs each "
                       f"({pairs} pairs, {dt:.1f} s)"}
 
 
-def bench_batch(args):
-    from paper_1411_3691_amd import workloads as W
-    shapes = W.batch_shapes()
-    ws = [W.batch_job(j, shapes[j]) for j in range(len(shapes))]
-    cpu = None if args.no_cpu_baseline else cpu_baseline_batch(ws)
+def run_timed(run, steps: int, warmup: int):
+    """W untimed calls, then K timed calls bracketed by device syncs: the
+    wall time of the K calls and each call's HIP-event time (ms) on torch's
+    current stream, the launch stream of the library's kernels."""
+    import torch
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        run()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [a.elapsed_time(b) for a, b in evs]
 
+
+def roofline(flops: float, kernel_ms: float, traffic=None) -> dict:
+    ach = flops / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / FP64_PEAK_TFLOPS, "traffic": traffic}
+
+
+def bench_batch(args, steps: int, warmup: int, plain_steps: int, plain_warmup: int,
+                cpu=None, with_pruned: bool = False) -> dict:
+    """The 256-job batch: one graph launch per step, on the autotuner's
+    cached schedule for these shapes (the library's default when the cache
+    has no entry)."""
     import numpy as np
     import torch
-    from paper_1411_3691_amd import mhc
+    from paper_1411_3691_amd import autotune, mhc
+    from paper_1411_3691_amd import workloads as W
 
+    shapes = W.batch_shapes()
+    ws = [W.batch_job(j, shapes[j]) for j in range(len(shapes))]
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
     plans, S, a, b, C = [], [], [], [], []
     fl_tree = fl_plain = 0.0
     t0 = time.perf_counter()
@@ -254,114 +294,90 @@ def bench_batch(args):
         C.append(torch.empty(w.T, dtype=torch.complex128, device=dev))
     t_plan = time.perf_counter() - t0
     pairs = sum(w.n_pairs for w in ws)
+    Ts = [w.T for w in ws]
     torch.cuda.synchronize()
+    log(f"batch: {len(ws)} plans built in {t_plan:.1f} s")
 
-    def timed(method):
-        batch = mhc.Batch(plans, [w.T for w in ws], method)
-        for _ in range(args.warmup):
-            batch.run(S, a, b, C)
-        torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
-        t0 = time.perf_counter()
-        for e0, e1 in evs:
-            e0.record()
-            batch.run(S, a, b, C)
-            e1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        per = [e0.elapsed_time(e1) for e0, e1 in evs]
-        return wall, float(np.mean(per)), [c.cpu().numpy().copy() for c in C], batch.info()
+    def timed(method, sched, k, wu):
+        batch = mhc.Batch(plans, Ts, method, sched)
+        wall, ev = run_timed(lambda: batch.run(S, a, b, C), k, wu)
+        return wall, float(np.mean(ev)), [c.cpu().numpy().copy() for c in C], batch.info()
 
-    wall_tree, ev_tree, C_tree, info = timed("tree")
-    wall_plain, ev_plain, C_plain, _ = timed("plain")
+    cache = os.path.join(ROOT, "paper_1411_3691_amd", "schedules.json")
+    if args.tune_cache:
+        # time every candidate schedule and store the choices (slow)
+        for method in ("tree", "plain"):
+            log(f"batch: tuning the {method} schedule")
+            autotune.tune(plans, Ts, method, S, a, b, cache=args.tune_cache, verbose=True)
+        cache = args.tune_cache
+    sched_tree = autotune.cached(plans, Ts, "tree", cache)
+    sched_plain = autotune.cached(plans, Ts, "plain", cache)
+    wall_tree, ev_tree, C_tree, info = timed("tree", sched_tree, steps, warmup)
+    log(f"batch: tree {wall_tree / steps:.3f} s per step")
+    wall_plain, ev_plain, C_plain, _ = timed("plain", sched_plain, plain_steps, plain_warmup)
+    log(f"batch: plain {wall_plain / plain_steps:.3f} s per step")
     rel = max(float(np.max(np.abs(x - y)) / max(1e-300, float(np.max(np.abs(y)))))
               for x, y in zip(C_tree, C_plain))
-    # every job's tree on its reverse-delete dominating set
-    plans_main, plans = plans, []
-    fl_pr, n_dom_g, n_dom_p = 0.0, 0, 0
-    for w, pm in zip(ws, plans_main):
-        terms = mhc.Terms(w.src, w.nf, w.M)
-        tree = mhc.Tree(terms, prune=True)
-        plans.append(mhc.Plan(tree, mhc.Terms(w.snk, w.nf, w.M)))
-        fl_pr += tree_flops(w.T, len(w.snk), w.nf, tree.export())
-        n_dom_p += tree.stats()["n_dom"]
-        n_dom_g += mhc.Tree(terms).stats()["n_dom"]
-    wall_pr, ev_pr, C_pr, _ = timed("tree")
-    plans = plans_main
-    pruned = {"value": pairs / (wall_pr / args.steps),
-              "ms_per_step": wall_pr * 1e3 / args.steps, "kernel_ms": ev_pr,
-              "n_dom": n_dom_p, "n_dom_greedy": n_dom_g, "flops_per_step": fl_pr,
-              "tflops": fl_pr / (ev_pr * 1e-3) / 1e12,
-              "max_rel_diff_vs_plain": max(
-                  float(np.max(np.abs(x - y)) / max(1e-300, float(np.max(np.abs(y)))))
-                  for x, y in zip(C_pr, C_plain))}
-    ach = fl_tree / (ev_tree * 1e-3) / 1e12
+    pruned = None
+    if with_pruned:
+        # every job's tree on its reverse-delete dominating set
+        plans_main, plans = plans, []
+        fl_pr, n_dom_g, n_dom_p = 0.0, 0, 0
+        for w in ws:
+            terms = mhc.Terms(w.src, w.nf, w.M)
+            tree = mhc.Tree(terms, prune=True)
+            plans.append(mhc.Plan(tree, mhc.Terms(w.snk, w.nf, w.M)))
+            fl_pr += tree_flops(w.T, len(w.snk), w.nf, tree.export())
+            n_dom_p += tree.stats()["n_dom"]
+            n_dom_g += mhc.Tree(terms).stats()["n_dom"]
+        wall_pr, ev_pr, C_pr, _ = timed("tree", sched_tree, steps, warmup)
+        plans = plans_main
+        pruned = {"value": pairs / (wall_pr / steps), "ms_per_step": wall_pr * 1e3 / steps,
+                  "kernel_ms": ev_pr, "n_dom": n_dom_p, "n_dom_greedy": n_dom_g,
+                  "flops_per_step": fl_pr, "tflops": fl_pr / (ev_pr * 1e-3) / 1e12,
+                  "max_rel_diff_vs_plain": max(
+                      float(np.max(np.abs(x - y)) / max(1e-300, float(np.max(np.abs(y)))))
+                      for x, y in zip(C_pr, C_plain))}
     nfs = sorted({n for w in ws for n in w.nf})
-    out = {
+    return {
         "metric": METRIC,
-        "value": pairs / (wall_tree / args.steps),
+        "value": pairs / (wall_tree / steps),
         "unit": "det-pairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall_tree * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall_tree * 1e3 / steps,
         "config": {
             "workload": f"batch: {len(ws)} jobs, flavour blocks {nfs[0]}..{nfs[-1]}, "
                         f"T 8..64, M 24/48/96, 50..5000 tree terms per side",
             "pairs_per_step": pairs,
             "method": "update tree (greedy R2 dominating set), one graph launch",
+            "schedule_tree": sched_tree, "schedule_plain": sched_plain,
         },
-        "plain_lu": {"value": pairs / (wall_plain / args.steps),
-                     "ms_per_step": wall_plain * 1e3 / args.steps, "kernel_ms": ev_plain,
+        "plain_lu": {"value": pairs / (wall_plain / plain_steps),
+                     "ms_per_step": wall_plain * 1e3 / plain_steps, "kernel_ms": ev_plain,
+                     "steps": plain_steps, "warmup": plain_warmup,
                      "flops_per_step": fl_plain,
                      "tflops": fl_plain / (ev_plain * 1e-3) / 1e12},
-        "speedup_vs_plain": wall_plain / wall_tree,
+        "speedup_vs_plain": (wall_plain / plain_steps) / (wall_tree / steps),
         "tree_vs_plain_max_rel_diff": rel,
         "tree": {"kernel_ms": ev_tree, "flops_per_step": fl_tree, "plan_s": t_plan, **info},
         "tree_pruned_dominators": pruned,
-        "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None},
+        "roofline": roofline(fl_tree, ev_tree),
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mid")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="one 256 MiB device-to-device copy before timing (a kernel of "
-                         "known traffic for scaling hardware byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the contraction has no multi-GPU path "
-              "in this library (run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-
-    if args.workload == "batch":
-        bench_batch(args)
-        return
-    from paper_1411_3691_amd import workloads as W
-    w = W.workload(args.workload)
-    # CPU leg first, before the process touches the GPU
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
-
+def bench_workload(w, args, steps: int, warmup: int, plain_steps: int, plain_warmup: int,
+                   cpu=None, extras: bool = True, settle: bool = True, probe: bool = True) -> dict:
+    """One workload: the update tree (K timed calls after W warm-ups) and the
+    plain LU; with ``extras`` also the paper's ablations (mid), the
+    reverse-delete dominating set, the adjoint (grad) and the two-sided
+    trees (one block size <= 8)."""
     import numpy as np
     import torch
     from paper_1411_3691_amd import mhc
 
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
     t0 = time.perf_counter()
     src = mhc.Terms(w.src, w.nf, w.M)
     snk = mhc.Terms(w.snk, w.nf, w.M)
@@ -381,111 +397,98 @@ def main():
         torch.cuda.synchronize()
         del a_, b_
     torch.cuda.synchronize()
+    name = w.name
 
     # The GPU raises its clocks over the first tens of milliseconds of
     # sustained work (back-to-back launches of one kernel run about 10 %
     # faster after ~50 ms): run the update tree untimed for SETTLE_S seconds
     # before the first timed method, then W warm-up steps per method.
-    t_settle = time.perf_counter()
-    while time.perf_counter() - t_settle < SETTLE_S:
-        mhc.contract_into(plan, S, ws, wk, C, "tree")
-        torch.cuda.synchronize()
+    if settle:
+        t_settle = time.perf_counter()
+        while time.perf_counter() - t_settle < SETTLE_S:
+            mhc.contract_into(plan, S, ws, wk, C, "tree")
+            torch.cuda.synchronize()
 
-    probe = fma_probe(dev)
+    fma = fma_probe(dev) if probe else None
 
-    def timed(method):
-        for _ in range(args.warmup):
-            mhc.contract_into(plan, S, ws, wk, C, method)
-        torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
-        t0 = time.perf_counter()
-        for a, b in evs:
-            a.record()
-            mhc.contract_into(plan, S, ws, wk, C, method)
-            b.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        per = [a.elapsed_time(b) for a, b in evs]          # ms, on the launch stream
+    cur = {"plan": plan}
+
+    def timed(method, k=steps, wu=warmup):
+        p = cur["plan"]
+        wall, per = run_timed(lambda: mhc.contract_into(p, S, ws, wk, C, method), k, wu)
         return wall, per, C.cpu().numpy().copy()
 
     wall_tree, ev_tree, C_tree = timed("tree")
-    wall_plain, ev_plain, C_plain = timed("plain")
+    log(f"{name}: tree {wall_tree * 1e3 / steps:.3f} ms per step")
+    wall_plain, ev_plain, C_plain = timed("plain", plain_steps, plain_warmup)
+    log(f"{name}: plain {wall_plain * 1e3 / plain_steps:.3f} ms per step")
     fl_tree = tree_flops(w.T, len(w.snk), w.nf, tree.export())
     # blocks of at most 8 take the lane-per-matrix kernels, whose solves
     # skip the zero head of e_r
-    narrow = max(w.nf) <= 8
+    narrow = len(set(w.nf)) == 1 and max(w.nf) <= 8
     fl_tree_exec = (tree_flops(w.T, len(w.snk), w.nf, tree.export(), executed=True)
                     if narrow else None)
     abl = None
-    if args.workload == "mid":
+    if extras and name == "mid":
         # the paper's variants (Sec. 4, Fig. 1 caption) on the same inputs:
         # LU without pivoting, and updates without shared solves; and LU
         # with threshold partial pivoting
         abl = {}
-        for name, method in (("plain_unpivoted", "plain_unpivoted"),
-                             ("tree_unpivoted", "tree_unpivoted"),
-                             ("plain_threshold_pivoting", "plain_threshold"),
-                             ("tree_threshold_pivoting", "tree_threshold")):
+        for lbl, method in (("plain_unpivoted", "plain_unpivoted"),
+                            ("tree_unpivoted", "tree_unpivoted"),
+                            ("plain_threshold_pivoting", "plain_threshold"),
+                            ("tree_threshold_pivoting", "tree_threshold")):
             wall_a, ev_a, _ = timed(method)
-            abl[name] = {"ms_per_step": wall_a * 1e3 / args.steps,
-                         "kernel_ms": float(np.mean(ev_a)),
-                         "value": w.n_pairs / (wall_a / args.steps)}
+            abl[lbl] = {"ms_per_step": wall_a * 1e3 / steps,
+                        "kernel_ms": float(np.mean(ev_a)),
+                        "value": w.n_pairs / (wall_a / steps)}
             if method == "tree_threshold":
                 a_t = fl_tree / (float(np.mean(ev_a)) * 1e-3) / 1e12
-                abl[name]["tflops"] = a_t
-                abl[name]["frac"] = a_t / FP64_PEAK_TFLOPS
+                abl[lbl]["tflops"] = a_t
+                abl[lbl]["frac"] = a_t / FP64_PEAK_TFLOPS
         tree_ns = mhc.Tree(src, share=False)
-        plan_ns = mhc.Plan(tree_ns, snk)
-        plan_main = plan
-        plan = plan_ns
+        cur["plan"] = mhc.Plan(tree_ns, snk)
         wall_a, ev_a, _ = timed("tree")
-        plan = plan_main
-        abl["tree_without_sharing"] = {"ms_per_step": wall_a * 1e3 / args.steps,
+        cur["plan"] = plan
+        abl["tree_without_sharing"] = {"ms_per_step": wall_a * 1e3 / steps,
                                        "kernel_ms": float(np.mean(ev_a)),
-                                       "value": w.n_pairs / (wall_a / args.steps),
+                                       "value": w.n_pairs / (wall_a / steps),
                                        "n_groups": tree_ns.stats()["n_groups"]}
-    if args.workload in ("mid", "large"):
+        log(f"{name}: ablations done")
+    if extras and name in ("mid", "large"):
         # reverse-delete dominating set: fewer dominators, same sum
         abl = abl if abl is not None else {}
-        plan_main = plan
         tree_pr = mhc.Tree(src, prune=True)
-        plan = mhc.Plan(tree_pr, snk)
+        cur["plan"] = mhc.Plan(tree_pr, snk)
         wall_a, ev_a, C_pr = timed("tree")
-        plan = plan_main
+        cur["plan"] = plan
         fl_pr = tree_flops(w.T, len(w.snk), w.nf, tree_pr.export())
         st_pr = tree_pr.stats()
         abl["tree_pruned_dominators"] = {
-            "ms_per_step": wall_a * 1e3 / args.steps,
+            "ms_per_step": wall_a * 1e3 / steps,
             "kernel_ms": float(np.mean(ev_a)),
-            "value": w.n_pairs / (wall_a / args.steps),
+            "value": w.n_pairs / (wall_a / steps),
             "n_dom": st_pr["n_dom"], "n_groups": st_pr["n_groups"],
             "flops_per_step": fl_pr,
             "tflops": fl_pr / (float(np.mean(ev_a)) * 1e-3) / 1e12,
             "max_rel_diff_vs_tree": float(np.max(np.abs(C_pr - C_tree))
                                           / max(1e-300, float(np.max(np.abs(C_tree)))))}
+        log(f"{name}: reverse-delete dominating set done")
     back = None
-    if args.workload == "grad":
+    if extras and name == "grad":
         # the adjoint (mhc_contract_backward): grad S and both weight
         # gradients for a random upstream gradient
         gC = torch.from_numpy(np.random.default_rng(0).standard_normal(w.T)
                               + 1j * np.random.default_rng(1).standard_normal(w.T)).to(dev)
         back = {}
         for bm in ("tree", "plain"):
-            for _ in range(args.warmup):
-                mhc.contract_backward(plan, S, ws, wk, gC, bm)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(args.steps):
-                mhc.contract_backward(plan, S, ws, wk, gC, bm)
-            e1.record()
-            torch.cuda.synchronize()
-            ms_b = e0.elapsed_time(e1) / args.steps
-            back[bm] = {"ms_per_step": ms_b, "det_pairs_per_s": w.n_pairs / (ms_b * 1e-3)}
+            wall_b, ev_b = run_timed(lambda: mhc.contract_backward(plan, S, ws, wk, gC, bm),
+                                     steps, warmup)
+            ms_b = float(np.mean(ev_b))
+            back[bm] = {"ms_per_step": wall_b * 1e3 / steps, "kernel_ms": ms_b,
+                        "det_pairs_per_s": w.n_pairs / (ms_b * 1e-3)}
     two = None
-    if len(set(w.nf)) == 1 and w.nf[0] <= 8:
+    if extras and narrow:
         # the two-sided extension: sink terms in their own update tree
         t0 = time.perf_counter()
         stree = mhc.Tree(snk)
@@ -495,11 +498,11 @@ def main():
         ev_two_ms = float(np.mean(ev_two))
         fl_two = two_sided_flops(w.T, w.nf, tree.export(), stree.export())
         ach_two = fl_two / (ev_two_ms * 1e-3) / 1e12
-        two = {"value": w.n_pairs / (wall_two / args.steps),
-               "ms_per_step": wall_two * 1e3 / args.steps, "kernel_ms": ev_two_ms,
+        two = {"value": w.n_pairs / (wall_two / steps),
+               "ms_per_step": wall_two * 1e3 / steps, "kernel_ms": ev_two_ms,
                "flops_per_step": fl_two, "tflops": ach_two,
                "frac": ach_two / FP64_PEAK_TFLOPS,
-               "speedup_vs_plain": wall_plain / wall_two,
+               "speedup_vs_plain": (wall_plain / plain_steps) / (wall_two / steps),
                "speedup_vs_one_sided": wall_tree / wall_two,
                "max_rel_diff_vs_plain": float(np.max(np.abs(C_two - C_plain)) /
                                               max(1e-300, float(np.max(np.abs(C_plain))))),
@@ -509,71 +512,144 @@ def main():
         tree_p2, stree_p2 = mhc.Tree(src, prune=True), mhc.Tree(snk, prune=True)
         plan_p2 = mhc.Plan(tree_p2, snk)
         plan_p2.attach_sink_tree(stree_p2)
-        plan_main = plan
-        plan = plan_p2
+        cur["plan"] = plan_p2
         wall_p2, ev_p2, C_p2 = timed("tree2")
-        plan = plan_main
+        cur["plan"] = plan
         fl_p2 = two_sided_flops(w.T, w.nf, tree_p2.export(), stree_p2.export())
         two["pruned_dominators"] = {
-            "value": w.n_pairs / (wall_p2 / args.steps),
-            "ms_per_step": wall_p2 * 1e3 / args.steps,
+            "value": w.n_pairs / (wall_p2 / steps),
+            "ms_per_step": wall_p2 * 1e3 / steps,
             "kernel_ms": float(np.mean(ev_p2)),
             "n_dom_src": tree_p2.stats()["n_dom"], "n_dom_snk": stree_p2.stats()["n_dom"],
             "flops_per_step": fl_p2,
             "tflops": fl_p2 / (float(np.mean(ev_p2)) * 1e-3) / 1e12,
             "max_rel_diff_vs_plain": float(np.max(np.abs(C_p2 - C_plain)) /
                                            max(1e-300, float(np.max(np.abs(C_plain)))))}
+        log(f"{name}: two-sided trees done")
     pairs = w.n_pairs
-    ms_tree = wall_tree * 1e3 / args.steps
-    ms_plain = wall_plain * 1e3 / args.steps
     ev_tree_ms = float(np.mean(ev_tree))
     ev_plain_ms = float(np.mean(ev_plain))
     fl_plain = plain_flops(w.T, len(w.src), len(w.snk), w.nf)
-    ach = fl_tree / (ev_tree_ms * 1e-3) / 1e12
     rel = float(np.max(np.abs(C_tree - C_plain)) / max(1e-300, float(np.max(np.abs(C_plain)))))
-
+    rf = roofline(fl_tree, ev_tree_ms, measured_traffic(name))
     out = {
         "metric": METRIC,
-        "value": pairs / (wall_tree / args.steps),
+        "value": pairs / (wall_tree / steps),
         "unit": "det-pairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_tree,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall_tree * 1e3 / steps,
         "config": {
-            "workload": f"{args.workload}: T={w.T} slices, M={w.M}, flavour blocks "
+            "workload": f"{name}: T={w.T} slices, M={w.M}, flavour blocks "
                         f"{list(w.nf)}, {len(w.src)} x {len(w.snk)} single-substitution "
                         f"tree terms",
             "pairs_per_step": pairs,
             "method": "update tree (greedy R2 dominating set)",
         },
-        "plain_lu": {"value": pairs / (wall_plain / args.steps), "ms_per_step": ms_plain,
-                     "kernel_ms": ev_plain_ms,
+        "plain_lu": {"value": pairs / (wall_plain / plain_steps),
+                     "ms_per_step": wall_plain * 1e3 / plain_steps,
+                     "kernel_ms": ev_plain_ms, "steps": plain_steps, "warmup": plain_warmup,
                      "flops_per_step": fl_plain,
                      "tflops": fl_plain / (ev_plain_ms * 1e-3) / 1e12},
-        "speedup_vs_plain": (wall_plain / wall_tree),
+        "speedup_vs_plain": (wall_plain / plain_steps) / (wall_tree / steps),
         "tree_vs_plain_max_rel_diff": rel,
         "tree": {**st, "rho": st["n_dom"] / st["n_terms"], "build_s": t_tree,
                  "kernel_ms": ev_tree_ms, "flops_per_step": fl_tree,
                  "flops_executed_per_step": fl_tree_exec,
                  "frac_executed": (fl_tree_exec / (ev_tree_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
                                    if narrow else None)},
-        "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(args.workload)},
-        "fp64_fma_probe": {"tflops": probe, "frac_of_peak": probe / FP64_PEAK_TFLOPS,
-                           "tree_frac_of_probe": ach / probe},
+        "roofline": rf,
         "cpu_baseline": cpu,
-        "two_sided": two,
-        "ablations": abl,
-        "backward": back,
     }
-    print(json.dumps(out), flush=True)
+    if fma is not None:
+        out["fp64_fma_probe"] = {"tflops": fma, "frac_of_peak": fma / FP64_PEAK_TFLOPS,
+                                 "tree_frac_of_probe": rf["achieved"] / fma}
+    if extras:
+        out["two_sided"] = two
+        out["ablations"] = abl
+        out["backward"] = back
+    return out
+
+
+def headline(obj: dict, args) -> dict:
+    """The contract's top-level fields around one workload's object."""
+    out = {"metric": obj["metric"], "value": obj["value"], "unit": obj["unit"],
+           "n_gpus": 1, "steps": obj["steps"], "warmup": obj["warmup"],
+           "ms_per_step": obj["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+    out.update({k: v for k, v in obj.items() if k not in out})
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=None,
+                    help="mid | large | batch | grad: that workload alone (default: mid "
+                         "with the large and batch sub-objects)")
+    ap.add_argument("--large-steps", type=int, default=3)
+    ap.add_argument("--large-warmup", type=int, default=1)
+    ap.add_argument("--large-plain-steps", type=int, default=1)
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-warmup", type=int, default=1)
+    ap.add_argument("--batch-plain-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="batch: run the autotuner for both methods first and store its "
+                         "choices in this JSON file")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="one 256 MiB device-to-device copy before timing (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the contraction has no multi-GPU path "
+              "in this library (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1411_3691_amd import workloads as W
+    wl = args.workload
+    # CPU legs first, before the process touches the GPU (the oracle's
+    # worker processes are forked)
+    cpu = {}
+    if not args.no_cpu_baseline:
+        if wl in (None, "mid", "large", "grad"):
+            for name in ([wl] if wl else ["mid", "large"]):
+                log(f"{name}: CPU oracle sample")
+                cpu[name] = cpu_baseline(W.workload(name), 15.0 if name == "mid" else 10.0)
+        if wl in (None, "batch"):
+            log("batch: CPU oracle sample (16 jobs)")
+            shapes = W.batch_shapes()
+            cpu["batch"] = cpu_baseline_batch([W.batch_job(j, shapes[j]) for j in range(16)])
+
+    import torch
+    torch.cuda.set_device(0)
+    if wl == "batch":
+        out = bench_batch(args, args.steps, args.warmup, args.steps, args.warmup,
+                          cpu.get("batch"), with_pruned=True)
+        print(json.dumps(headline(out, args)), flush=True)
+        return
+    if wl is not None:
+        out = bench_workload(W.workload(wl), args, args.steps, args.warmup, args.steps,
+                             args.warmup, cpu.get(wl))
+        print(json.dumps(headline(out, args)), flush=True)
+        return
+    # default: the mid headline, then the large and batch workloads
+    log("mid: headline")
+    out = bench_workload(W.workload("mid"), args, args.steps, args.warmup, args.steps,
+                         args.warmup, cpu.get("mid"))
+    log("large: full workload")
+    large = bench_workload(W.workload("large"), args, args.large_steps, args.large_warmup,
+                           args.large_plain_steps, 0, cpu.get("large"), extras=False,
+                           settle=False, probe=False)
+    log("batch: 256 jobs")
+    batch = bench_batch(args, args.batch_steps, args.batch_warmup, args.batch_plain_steps, 0,
+                        cpu.get("batch"))
+    line = headline(out, args)
+    line["large"] = large
+    line["batch"] = batch
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

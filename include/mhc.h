@@ -227,6 +227,23 @@ mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
                         void* pair_det, const int32_t* pairs, int64_t n_pairs,
                         void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward contraction of mhc_contract without the pair-determinant hook,
+ * with the workgroup partial sums in a static device array of the library
+ * (2 MiB per device, held until the process ends) instead of a buffer
+ * grown on the plan.  It calls no hipMalloc or hipFree; its first call on a
+ * device only looks up that array's address there.  Every valid T fits (the
+ * partials take at most 3 * (4096 + T) doubles); a call that would need
+ * more returns MHC_E_UNSUPPORTED.  All calls on one device share the array
+ * and its contents: calls that overlap in time on one device (different
+ * streams, threads or plans) race.  Arguments, methods and errors as for
+ * mhc_contract. */
+mhc_status mhc_contract_noalloc(mhc_plan* plan, int32_t method, int32_t T,
+                                const void* S, const double* w_src,
+                                const double* w_snk, void* C, double* A,
+                                void* stream);
+
 /* Adjoint of mhc_contract (every method computes the same C).  For an
  * incoming gradient gC of a real loss (PyTorch's convention for complex
  * tensors):
@@ -244,9 +261,10 @@ mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
  * be NULL (not written).  At most 4 flavour blocks of one size n <= 8; S_t
  * and its gradient must fit in LDS together (2 * M * (M + 1) * 16 bytes).
  * A pair's flavour block with an exactly zero pivot (for MHC_UPDATE_TREE:
- * every pair of a dominator whose block has one) is taken pair by pair, and
- * a block that stays singular contributes nothing to gS and is counted
- * (mhc_plan_status).  Device scratch is allocated on the plan at the first
+ * every pair of a dominator whose block has one) is taken pair by pair; a
+ * block that stays singular has no inverse, and its cofactors come from its
+ * minors (the definition of the adjugate, by direct LU of each minor); such
+ * blocks are counted (mhc_plan_status).  Device scratch is allocated on the plan at the first
  * call (and grown when T grows). */
 mhc_status mhc_contract_backward(mhc_plan* plan, int32_t method, int32_t T, const void* S,
                                  const double* w_src, const double* w_snk,
@@ -254,13 +272,15 @@ mhc_status mhc_contract_backward(mhc_plan* plan, int32_t method, int32_t T, cons
                                  double* g_wsnk, void* stream);
 
 /* Counters summed over all completed calls on this plan (either pointer may
- * be NULL); synchronises the device first.
+ * be NULL); synchronises the device first.  They count the work the update
+ * route of Sec. 2 cannot take (the matrix determinant lemma needs the
+ * dominator's inverse), which goes by direct LU instead.
  *   n_fallback       work the update paths took by direct LU because a
  *                    dominator block had an exactly zero pivot (no
  *                    inverse): children (MHC_UPDATE_TREE), or (source
  *                    dominator, sink dominator) pairs (MHC_UPDATE_TREE2);
- *   n_singular_grad  (pair, flavour) blocks with an exactly zero pivot that
- *                    the adjoint skipped. */
+ *   n_singular_grad  (pair, flavour) blocks with an exactly zero pivot whose
+ *                    cofactors the adjoint took from their minors. */
 mhc_status mhc_plan_status(mhc_plan* plan, int64_t* n_fallback,
                            int64_t* n_singular_grad);
 

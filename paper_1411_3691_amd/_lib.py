@@ -64,6 +64,7 @@ SIGNATURES = {
     "mhc_plan_create": (_I32, [_P, _P, _P, ctypes.POINTER(_P)]),
     "mhc_plan_destroy": (None, [_P]),
     "mhc_contract": (_I32, [_P, _I32, _I32, _P, _PD, _PD, _P, _PD, _P, _P, _I64, _P]),
+    "mhc_contract_noalloc": (_I32, [_P, _I32, _I32, _P, _PD, _PD, _P, _PD, _P]),
     "mhc_contract_backward": (_I32, [_P, _I32, _I32, _P, _PD, _PD, _P, _P, _PD, _PD, _P]),
     "mhc_plan_status": (_I32, [_P, _PI64, _PI64]),
     "mhc_plan_attach_sink_tree": (_I32, [_P, _P, _P]),

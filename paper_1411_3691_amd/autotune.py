@@ -17,6 +17,7 @@ import hashlib
 import itertools
 import json
 import os
+import sys
 import time
 
 DEFAULT_GRID = {
@@ -64,6 +65,13 @@ def store_cache(path: str, key: str, entry: dict) -> None:
     os.replace(tmp, path)
 
 
+def cached(plans, T, method: str, cache: str | None) -> dict | None:
+    """The schedule stored in ``cache`` for this batch's shapes, or None (the
+    library then chooses); never times anything."""
+    hit = load_cache(cache).get(shape_key(plans, T, method))
+    return dict(hit["schedule"]) if hit is not None else None
+
+
 def tune(plans, T, method, S, w_src, w_snk, cache: str | None = None,
          grid: dict | None = None, reps: int = 3, verbose: bool = False) -> dict:
     """The fastest schedule for this batch (read from ``cache`` when the
@@ -93,7 +101,7 @@ def tune(plans, T, method, S, w_src, w_snk, cache: str | None = None,
         ms = e0.elapsed_time(e1) / reps
         results.append((ms, sc))
         if verbose:
-            print(f"autotune {sc}: {ms:.3f} ms", flush=True)
+            print(f"autotune {sc}: {ms:.3f} ms", file=sys.stderr, flush=True)
         del batch
     ms, best = min(results, key=lambda r: r[0])
     if cache:

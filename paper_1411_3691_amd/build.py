@@ -28,6 +28,7 @@ COMMON = [
 ]
 
 SOURCES = ["mhc_host.cpp", "mhc_plan.hip", "contract_kernels.hip", "wide_kernels.hip",
+           "wide_b8.hip", "wide_b12.hip", "wide_b16.hip", "wide_b18.hip", "wide_b24.hip",
            "adjoint_kernels.hip", "tree2_kernels.hip", "probe_kernels.hip", "pair_kernels.hip"]
 
 
@@ -60,7 +61,7 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     their objects or older than a header) and links libmhc.so; returns its
     path."""
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]

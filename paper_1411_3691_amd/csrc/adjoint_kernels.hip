@@ -57,13 +57,55 @@ __device__ __forceinline__ void grad_add(char* glds, uint32_t plane, uint32_t ro
   atomicAdd(reinterpret_cast<double*>(e + plane), im);
 }
 
+// Block with an exactly zero pivot (no inverse): its cofactors from the
+// definition, adj(G)[n][r] = (-1)^(r+n) det(G without row r and column n),
+// each minor by a direct LU (Jacobi's formula d det G / d G[r][n] =
+// adj(G)[n][r] holds for singular G too).  Scatters b * conj(adj(G)[n][r])
+// into grad S at (row r, column n) for the lanes with `valid`; b = coef *
+// conj(prod of the other blocks' determinants).  Rare (singular blocks
+// only), so the minor loop is not unrolled.
+template <int N>
+__device__ __noinline__ void scatter_cofactors(const char* lds, char* glds, uint32_t plane,
+                                               const uint32_t (&ro)[N], const uint32_t (&co)[N],
+                                               double bre, double bim, bool valid) {
+  if constexpr (N == 1) {
+    if (valid) grad_add(glds, plane, ro[0], co[0], bre, bim);
+  } else {
+#pragma unroll 1
+    for (int r = 0; r < N; ++r) {
+#pragma unroll 1
+      for (int n = 0; n < N; ++n) {
+        uint32_t rm[N - 1], cm[N - 1];
+#pragma unroll
+        for (int m = 0; m < N - 1; ++m) {
+          rm[m] = m < r ? ro[m] : ro[m + 1];
+          cm[m] = m < n ? co[m] : co[m + 1];
+        }
+        double gr[N - 1][N - 1], gi[N - 1][N - 1];
+        int perm[N - 1];
+        double mr, mi;
+        bool z;
+        gather<N - 1>(lds, rm, cm, gr, gi);
+        lu<N - 1, false>(gr, gi, mr, mi, perm, z);
+        if ((r + n) & 1) {
+          mr = -mr;
+          mi = -mi;
+        }
+        // grad S[row r][col n] += b * conj(adj[n][r])
+        if (valid) grad_add(glds, plane, ro[r], co[n], bre * mr + bim * mi, bim * mr - bre * mi);
+      }
+    }
+  }
+}
+
 // One source term against the lane's sink, pair by pair: the term's rows
 // are the row set `rowoff` with, in flavour fs, row rs replaced by the row
 // at byte offset srow (fs < 0: no replacement).  Pass 1 forms every block's
 // determinant; pass 2 refactorises each block, solves its N unit columns and
 // scatters coef * conj(X_f det_f) * conj(x_r[n]) into the LDS accumulator
 // (coef = gc * w_i * w_k).  Returns the pair determinant.  A block with an
-// exactly zero pivot is skipped in pass 2 and counted.
+// exactly zero pivot has no inverse: its cofactors come from its minors
+// (scatter_cofactors), and it is counted.
 template <int N>
 __device__ __forceinline__ double2 member_adjoint(const PlanView& p, const char* lds, char* glds,
                                                   const uint32_t* rowoff, int fs, int rs,
@@ -129,9 +171,11 @@ __device__ __forceinline__ double2 member_adjoint(const PlanView& p, const char*
     gather<N>(lds, ro, co, gr, gi);
     lu<N, true>(gr, gi, ddr, ddi, perm, z);
     if (z) {
-      // det_f = 0 exactly: its adjugate is not formed from an inverse;
-      // the block's contribution is skipped and counted
+      // no inverse: the cofactors from the minors, scaled by
+      // coef * conj(X_f) (det_f is not a factor of the adjugate)
       if (valid) ++n_singular;
+      scatter_cofactors<N>(lds, glds, grad_plane_bytes(p.M), ro, co, cre * xre + cim * xim,
+                           cim * xre - cre * xim, valid);
       continue;
     }
 #pragma unroll

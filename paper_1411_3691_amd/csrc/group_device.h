@@ -1,9 +1,9 @@
 // Device building blocks of the group kernels (one group of GROUP lanes per
 // matrix, one row per lane): DPP group reductions, the LDS handshake
 // between the lanes of a wave, Gauss-Jordan elimination with partial
-// pivoting by row relabelling, the replay of its row operations on a unit
-// column, and the direct determinant of a block with one row replaced.
-// Shared by the contraction kernels and the per-pair kernels.
+// pivoting by row relabelling that carries right-hand sides, and the direct
+// determinant of a block with one row replaced.  Shared by the contraction
+// kernels and the per-pair kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,38 +16,57 @@
 namespace mhc {
 namespace kern {
 
-// A double moved across lanes by a DPP row rotation (within each row of 16
-// lanes): lane i receives lane (i + R) mod 16 of its row.
-template <int R>
-__device__ __forceinline__ double row_ror(double v) {
-  constexpr int ctrl = 0x120 + R;   // DPP row_ror:R
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xf, 0xf, false);
+// A double moved across lanes by one DPP control (row_ror, quad_perm,
+// row_half_mirror): lane i receives the lane the control names within its
+// row of 16.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
 
-// Sum / max over the GROUP lanes of a group: rotations by 8, 4, 2, 1 within
-// each row of 16 (every lane forms the same pairs, so all lanes get the
-// same bits), then one exchange between the two rows of a 32-lane group.
+// DPP controls: row_ror:R rotates a row of 16 by R; quad_perm [1,0,3,2] and
+// [2,3,0,1] swap neighbours and pairs within each quad; row_half_mirror
+// reverses each half row of 8.
+constexpr int kDppRor8 = 0x128, kDppRor4 = 0x124, kDppRor2 = 0x122, kDppRor1 = 0x121;
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141;
+
+// Sum / max over the GROUP lanes of a group (8: three steps within each
+// half row; 16: rotations by 8, 4, 2, 1 within each row; 32: one more
+// exchange between the two rows).  Every lane combines the same values in
+// the same order up to commutation, so all lanes get the same bits.
 template <int GROUP>
 __device__ __forceinline__ double group_sum(double v) {
-  static_assert(GROUP == 16 || GROUP == 32, "groups are one or two DPP rows");
-  v += row_ror<8>(v);
-  v += row_ror<4>(v);
-  v += row_ror<2>(v);
-  v += row_ror<1>(v);
-  if (GROUP == 32) v += __shfl_xor(v, 16, 32);
+  static_assert(GROUP == 8 || GROUP == 16 || GROUP == 32, "groups are 8, 16 or 32 lanes");
+  if constexpr (GROUP == 8) {
+    v += dpp_move<kDppXor1>(v);
+    v += dpp_move<kDppXor2>(v);
+    v += dpp_move<kDppHalfMirror>(v);
+  } else {
+    v += dpp_move<kDppRor8>(v);
+    v += dpp_move<kDppRor4>(v);
+    v += dpp_move<kDppRor2>(v);
+    v += dpp_move<kDppRor1>(v);
+    if (GROUP == 32) v += __shfl_xor(v, 16, 32);
+  }
   return v;
 }
 
 template <int GROUP>
 __device__ __forceinline__ double group_max(double v) {
-  static_assert(GROUP == 16 || GROUP == 32, "groups are one or two DPP rows");
-  v = fmax(v, row_ror<8>(v));
-  v = fmax(v, row_ror<4>(v));
-  v = fmax(v, row_ror<2>(v));
-  v = fmax(v, row_ror<1>(v));
-  if (GROUP == 32) v = fmax(v, __shfl_xor(v, 16, 32));
+  static_assert(GROUP == 8 || GROUP == 16 || GROUP == 32, "groups are 8, 16 or 32 lanes");
+  if constexpr (GROUP == 8) {
+    v = fmax(v, dpp_move<kDppXor1>(v));
+    v = fmax(v, dpp_move<kDppXor2>(v));
+    v = fmax(v, dpp_move<kDppHalfMirror>(v));
+  } else {
+    v = fmax(v, dpp_move<kDppRor8>(v));
+    v = fmax(v, dpp_move<kDppRor4>(v));
+    v = fmax(v, dpp_move<kDppRor2>(v));
+    v = fmax(v, dpp_move<kDppRor1>(v));
+    if (GROUP == 32) v = fmax(v, __shfl_xor(v, 16, 32));
+  }
   return v;
 }
 
@@ -80,29 +99,37 @@ struct GJResult {
   bool zero;         // some pivot was exactly zero
 };
 
-// Pivot lanes of the elimination steps, 5 bits each.
-template <int NMAX>
-struct PivotLanes {
-  uint32_t w[(NMAX + 5) / 6];
-  __device__ __forceinline__ int get(int k) const { return (w[k / 6] >> (5 * (k % 6))) & 31; }
-};
+// Complex entries of one group's pivot-row buffer in LDS: the row and the
+// right-hand sides.
+template <int NMAX, int RMAX>
+constexpr int prow_entries() {
+  return NMAX + RMAX;
+}
 
-// Gauss-Jordan on the group's matrix.  (ar, ai)[c]: this lane's row
-// (columns c < n).  Step k eliminates column k from every row but the
-// pivot row; a row's multiplier l_{m,k} is kept in its column k (which
-// the elimination has just zeroed), so the row operations can be replayed
-// on any right-hand side afterwards (replay_unit).  On return, lane m < n
-// holds the reciprocal of its pivot in (ur, ui) and the column it pivoted
-// in (col); piv holds the pivot lane of every step.
-// LDS_BCAST: the pivot row goes through the group's LDS row buffer (the
-// factorisations of the main path); otherwise through ds_bpermute shuffles
-// (the direct factorisations of the zero-pivot route, where the LDS form,
-// inlined into the children loop, made the compiler keep far more
-// registers live).
-template <int GROUP, int NMAX, bool LDS_BCAST>
-__device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai)[NMAX], int n,
-                                                 int m, double& ur, double& ui, int& col,
-                                                 PivotLanes<NMAX>& piv, double2* prow) {
+// Gauss-Jordan elimination with partial pivoting on the group's matrix,
+// carrying right-hand sides.  Lane m < n holds row m: (ar, ai)[c] for the
+// columns c < n, and (br, bi)[q] for the right-hand sides q < nr (nr <=
+// RMAX, the same in every lane of the group; a lane's entry of b_q is row m
+// of that column).  Step k takes as pivot the row not used yet with the
+// largest |Re| + |Im| in column k (lowest row on ties: one DPP max over the
+// group, the lane rank packed into the low mantissa bits); every other row
+// subtracts l_m = a_mk / u times the pivot row from its columns above k and
+// from its right-hand sides.  Rows are relabelled, never moved.  A row that
+// was pivot keeps its pivot u_m in its column col_m (later steps only
+// subtract from columns above theirs), so at the end the system reads
+// u_m x[col_m] = b'_q[m]: lane m returns 1/u_m in (ur, ui) and col_m in col,
+// and x = G^-1 b_q has x[col_m] = b'_q[m] / u_m.  det G = sign of the pivot
+// order times the product of the pivots, the pivots of GEPP.  Columns <= k
+// of a row are not read after step k and are left as they are.
+// LDS_BCAST: the pivot row goes to the group's LDS buffer (prow,
+// prow_entries complex entries: the row from column k on, then the
+// right-hand sides) and every lane reads it back; otherwise every entry
+// moves by a ds_bpermute shuffle.
+template <int GROUP, int NMAX, int RMAX, bool LDS_BCAST>
+__device__ __forceinline__ GJResult gauss_jordan_rhs(double (&ar)[NMAX], double (&ai)[NMAX],
+                                                     double (&br)[RMAX], double (&bi)[RMAX],
+                                                     int nr, int n, int m, double& ur,
+                                                     double& ui, int& col, double2* prow) {
   static_assert(GROUP <= 32, "lane rank is packed into 5 bits");
   GJResult res{1.0, 0.0, false};
   bool done = m >= n;
@@ -111,7 +138,6 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
   ur = 0.0;
   ui = 0.0;
   col = -1;
-  static_for<0, (NMAX + 5) / 6>([&](auto ic) { piv.w[decltype(ic)::value] = 0u; });
   static_for<0, NMAX>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     if (k >= n) return;
@@ -123,13 +149,11 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
     // (some row of the group is always unused at step k < n, so the max
     // carries a rank 0 <= p < GROUP; the mask only keeps the lane in range)
     const int p = (31 - (int)(__double2loint(key) & 31u)) & (GROUP - 1);
-    piv.w[k / 6] |= (uint32_t)p << (5 * (k % 6));
     // sign: rows below p that are still unused each contribute one
     // transposition to the pivot permutation
     const uint64_t open = __builtin_amdgcn_ballot_w64(!done);
     const uint32_t below = (uint32_t)((open >> gbase) & ((1ull << p) - 1ull));
     neg = neg != ((__builtin_popcount(below) & 1) != 0);
-    // pivot row, broadcast to the group
     const bool me = (m == p);
     const int src = gbase + p;
     double pr, pi;
@@ -138,6 +162,10 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
         static_for<k, NMAX>([&](auto cc) {
           constexpr int c = decltype(cc)::value;
           if (c < n) prow[c] = make_double2(ar[c], ai[c]);
+        });
+        static_for<0, RMAX>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          if (q < nr) prow[NMAX + q] = make_double2(br[q], bi[q]);
         });
       }
       wave_lds_sync();
@@ -171,23 +199,38 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
     static_for<k + 1, NMAX>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
       if (c >= n) return;
-      double br, bi;
+      double sr, si;
       if constexpr (LDS_BCAST) {
         const double2 b = prow[c];
-        br = b.x;
-        bi = b.y;
+        sr = b.x;
+        si = b.y;
       } else {
-        br = __shfl(ar[c], src, 64);
-        bi = __shfl(ai[c], src, 64);
+        sr = __shfl(ar[c], src, 64);
+        si = __shfl(ai[c], src, 64);
       }
-      ar[c] = ar[c] - lr * br + li * bi;
-      ai[c] = ai[c] - lr * bi - li * br;
+      ar[c] = ar[c] - lr * sr + li * si;
+      ai[c] = ai[c] - lr * si - li * sr;
+      // at most four entries of the pivot row in flight: otherwise the
+      // compiler reads the whole row (up to NMAX + RMAX entries) ahead
+      if constexpr ((c - k) % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+    });
+    static_for<0, RMAX>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      if (q >= nr) return;
+      double sr, si;
+      if constexpr (LDS_BCAST) {
+        const double2 b = prow[NMAX + q];
+        sr = b.x;
+        si = b.y;
+      } else {
+        sr = __shfl(br[q], src, 64);
+        si = __shfl(bi[q], src, 64);
+      }
+      br[q] = br[q] - lr * sr + li * si;
+      bi[q] = bi[q] - lr * si - li * sr;
+      if constexpr (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
     });
     if constexpr (LDS_BCAST) wave_lds_sync();   // the row is read before the next step writes
-    if (!me) {
-      ar[k] = lr;
-      ai[k] = li;
-    }
   });
   if (neg) {
     res.dre = -res.dre;
@@ -196,66 +239,38 @@ __device__ __forceinline__ GJResult gauss_jordan(double (&ar)[NMAX], double (&ai
   return res;
 }
 
-// x = G^-1 e_r from an elimination: replays its row operations on the unit
-// column e_r (lane m holds entry m); then x[col_m] = E'_m / u_m, returned
-// in (xr, xi) by lane m.  The pivot lane of a step keeps its own column k
-// entry (its pivot), which the step does not use.
-template <int GROUP, int NMAX, bool LDS_BCAST>
-__device__ __forceinline__ void replay_unit(const double (&ar)[NMAX], const double (&ai)[NMAX],
-                                            const PivotLanes<NMAX>& piv, int r, int n, int m,
-                                            double ur, double ui, double& xr, double& xi,
-                                            double2* prow) {
-  const int gbase = (__lane_id() / GROUP) * GROUP;
-  double er = (m == r) ? 1.0 : 0.0, ei = 0.0;
-  static_for<0, NMAX>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    if (k >= n) return;
-    const int p = piv.get(k);
-    // the pivot lane's entry, broadcast to the group
-    double br, bi;
-    if constexpr (LDS_BCAST) {
-      if (m == p) prow[0] = make_double2(er, ei);
-      wave_lds_sync();
-      const double2 b = prow[0];
-      wave_lds_sync();
-      br = b.x;
-      bi = b.y;
-    } else {
-      br = __shfl(er, gbase + p, 64);
-      bi = __shfl(ei, gbase + p, 64);
-    }
-    if (m != p && m < n) {
-      er = er - ar[k] * br + ai[k] * bi;
-      ei = ei - ar[k] * bi - ai[k] * br;
-    }
-  });
-  xr = er * ur - ei * ui;
-  xi = er * ui + ei * ur;
-}
-
-// det of the block whose row `rrep` is replaced by the LDS row `newrow`
-// (direct elimination; used when the dominator block had a zero pivot).
-template <int GROUP, int NMAX>
-__device__ __forceinline__ void block_det_direct(const char* lds, uint32_t myrow, int rrep,
-                                                 uint32_t newrow, const uint32_t (&co)[NMAX],
-                                                 int n, int m, double& dre, double& dim,
-                                                 double2* prow) {
-  const uint32_t row = (m == rrep) ? newrow : myrow;
-  double ar[NMAX], ai[NMAX];
+// Loads this lane's row of the block G[m][c] = S_t[row m][col c] from the
+// LDS copy of S_t (lanes m >= n and columns c >= n get zeros).
+template <int NMAX>
+__device__ __forceinline__ void load_row(const char* lds, uint32_t myrow,
+                                         const uint32_t (&co)[NMAX], int n, int m,
+                                         double (&ar)[NMAX], double (&ai)[NMAX]) {
 #pragma unroll
   for (int c = 0; c < NMAX; ++c) {
     ar[c] = 0.0;
     ai[c] = 0.0;
     if (c < n && m < n) {
-      const double2 v = *reinterpret_cast<const double2*>(lds + row + co[c]);
+      const double2 v = *reinterpret_cast<const double2*>(lds + myrow + co[c]);
       ar[c] = v.x;
       ai[c] = v.y;
     }
   }
-  double ur, ui;
+}
+
+// det of the block whose row `rrep` is replaced by the LDS row `newrow`
+// (direct elimination, shuffle broadcasts; used when the dominator block had
+// a zero pivot).
+template <int GROUP, int NMAX>
+__device__ __forceinline__ void block_det_direct(const char* lds, uint32_t myrow, int rrep,
+                                                 uint32_t newrow, const uint32_t (&co)[NMAX],
+                                                 int n, int m, double& dre, double& dim) {
+  const uint32_t row = (m == rrep) ? newrow : myrow;
+  double ar[NMAX], ai[NMAX];
+  load_row<NMAX>(lds, row, co, n, m, ar, ai);
+  double ur, ui, b0r[1] = {0.0}, b0i[1] = {0.0};
   int col;
-  PivotLanes<NMAX> piv;
-  const GJResult g = gauss_jordan<GROUP, NMAX, false>(ar, ai, n, m, ur, ui, col, piv, prow);
+  const GJResult g =
+      gauss_jordan_rhs<GROUP, NMAX, 1, false>(ar, ai, b0r, b0i, 0, n, m, ur, ui, col, nullptr);
   dre = g.dre;
   dim = g.dim;
 }

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -43,6 +44,13 @@ struct mhc_plan {
   int32_t n_sdom = 0, n_sgroups = 0, n_schildren = 0;
 };
 
+// Workgroup partial sums of mhc_contract_noalloc: a file-scope device array
+// (each GPU the library runs on holds its own copy until the process ends),
+// so that entry point never allocates.  2 MiB covers every valid T: a call
+// needs T * ceil(4096 / T) * 3 <= 3 * (4096 + 65534) doubles.
+constexpr size_t kNoAllocScratchDoubles = size_t(1) << 18;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
 namespace {
 
 constexpr int kSinkBlock = 64;
@@ -62,6 +70,27 @@ size_t append(std::vector<char>& img, const std::vector<T>& v) {
   img.resize(at + std::max<size_t>(v.size() * sizeof(T), 1));
   if (!v.empty()) std::memcpy(img.data() + at, v.data(), v.size() * sizeof(T));
   return at;
+}
+
+// Device address of `scratch` on each device, taken once per device (with
+// that device current) by hipGetSymbolAddress: in host code the array's
+// name is only a host-side stand-in.
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
+
+mhc_status noalloc_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(MHC_E_DEVICE, "mhc_contract_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "mhc_contract_noalloc/hipGetSymbolAddress");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return MHC_OK;
 }
 
 }  // namespace
@@ -316,10 +345,14 @@ mhc_status mhc_plan_attach_sink_tree(mhc_plan* pl, const mhc_tree* st, void* str
   return MHC_OK;
 }
 
-mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
-                        const double* w_src, const double* w_snk, void* C,
-                        double* A, void* pair_det, const int32_t* pairs, int64_t n_pairs,
-                        void* stream) {
+// The forward contraction behind mhc_contract and mhc_contract_noalloc:
+// `fixed` (capacity fixed_cap doubles) replaces the plan's growing partial
+// buffer when not NULL.
+static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const void* S,
+                                const double* w_src, const double* w_snk, void* C,
+                                double* A, void* pair_det, const int32_t* pairs,
+                                int64_t n_pairs, void* stream, double* fixed,
+                                size_t fixed_cap) {
   if (!pl) return fail(MHC_E_ARG, "mhc_contract: NULL plan");
   if (!S || !w_src || !w_snk || !C)
     return fail(MHC_E_ARG, "mhc_contract: NULL buffer");
@@ -380,7 +413,13 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   n_blk_t = (int)std::min<long long>(n_blk_t, (n_items + waves_per_block - 1) / waves_per_block);
   n_blk_t = std::max(1, n_blk_t);
   const size_t need = (size_t)T * n_blk_t * 3;
-  if (need > pl->partial_cap) {
+  if (fixed) {
+    if (need > fixed_cap)
+      return fail(MHC_E_UNSUPPORTED,
+                  "mhc_contract_noalloc: the partial sums need " + std::to_string(need) +
+                      " doubles, more than the " + std::to_string(fixed_cap) +
+                      " of the static scratch");
+  } else if (need > pl->partial_cap) {
     if (pl->partial) {
       // earlier calls may still read the old buffer, on any stream
       e = hipDeviceSynchronize();
@@ -400,7 +439,7 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
   a.S = static_cast<const double2*>(S);
   a.w_src = w_src;
   a.w_snk = w_snk;
-  a.partial = pl->partial;
+  a.partial = fixed ? fixed : pl->partial;
   a.pair_det = static_cast<double2*>(dense_pairs);
   a.fallback = pl->fallback;
   a.T = T;
@@ -431,6 +470,31 @@ mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
     if (e != hipSuccess) return hip_fail(e, "mhc_contract/pairs");
   }
   return MHC_OK;
+}
+
+mhc_status mhc_contract(mhc_plan* pl, int32_t method, int32_t T, const void* S,
+                        const double* w_src, const double* w_snk, void* C,
+                        double* A, void* pair_det, const int32_t* pairs, int64_t n_pairs,
+                        void* stream) {
+  return contract_impl(pl, method, T, S, w_src, w_snk, C, A, pair_det, pairs, n_pairs, stream,
+                       nullptr, 0);
+}
+
+mhc_status mhc_contract_noalloc(mhc_plan* pl, int32_t method, int32_t T, const void* S,
+                                const double* w_src, const double* w_snk, void* C, double* A,
+                                void* stream) {
+  if (!pl) return fail(MHC_E_ARG, "mhc_contract_noalloc: NULL plan");
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "mhc_contract_noalloc/hipGetDevice");
+  if (cur != pl->device)
+    return fail(MHC_E_DEVICE, "mhc_contract_noalloc: current device differs from the plan's "
+                              "device");
+  double* ptr = nullptr;
+  const mhc_status st = noalloc_scratch(cur, &ptr);
+  if (st != MHC_OK) return st;
+  return contract_impl(pl, method, T, S, w_src, w_snk, C, A, nullptr, nullptr, 0, stream, ptr,
+                       kNoAllocScratchDoubles);
 }
 
 mhc_status mhc_contract_backward(mhc_plan* pl, int32_t method, int32_t T, const void* S,
@@ -678,7 +742,13 @@ mhc_status batch_build(mhc_batch* b) {
     const Bucket& bk = buckets[i];
     mhc::kern::BatchArgs ba{b->jobs_dev, tiles_dev + ranges[i].first, (int)ranges[i].second};
     int per_cu = b->sched.blocks_per_cu;
-    if (per_cu <= 0) per_cu = bk.lds > 72 * 1024 ? 1 : 2;
+    if (per_cu <= 0) {
+      // as many workgroups per compute unit as stay resident together: one
+      // 1024-thread group kernel (its waves fill the SIMDs), else two where
+      // two copies of the slice fit in LDS
+      const bool big = !bk.narrow && mhc::kern::wide_block(bk.n, tree, bk.lds) >= 1024;
+      per_cu = (big || bk.lds > 72 * 1024) ? 1 : 2;
+    }
     const int grid = std::max(1, std::min((int)ranges[i].second, n_cu * per_cu));
     le = bk.narrow
              ? mhc::kern::launch_batch_lane(ba, bk.n, tree, b->with_a, grid, bk.lds, b->cap)

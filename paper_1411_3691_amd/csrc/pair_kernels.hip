@@ -120,7 +120,8 @@ __global__ __launch_bounds__(kPairBlock) void pair_lane_kernel(PairArgs a) {
 }
 
 // One group of GROUP lanes per matrix, one row per lane (blocks up to NMAX,
-// sizes may differ per flavour), as in the group contraction kernels.
+// sizes may differ per flavour), as in the group contraction kernels: the
+// elimination carries e_r of the changed row as its right-hand side.
 template <int GROUP, int NMAX, bool TREE>
 __global__ __launch_bounds__(kPairBlock) void pair_group_kernel(PairArgs a) {
   const int q = (blockIdx.x * kPairBlock + threadIdx.x) / GROUP;
@@ -152,18 +153,20 @@ __global__ __launch_bounds__(kPairBlock) void pair_group_kernel(PairArgs a) {
         ai[c] = v.y;
       }
     }
-    double ur, ui;
+    // the changed row's unit column rides along as the one right-hand side
+    double ur, ui, b0r[1] = {(TREE && f == fc && m == rc) ? 1.0 : 0.0}, b0i[1] = {0.0};
     int col;
-    PivotLanes<NMAX> piv;
-    const GJResult res = gauss_jordan<GROUP, NMAX, false>(ar, ai, n, m, ur, ui, col, piv, nullptr);
+    const GJResult res = gauss_jordan_rhs<GROUP, NMAX, 1, false>(
+        ar, ai, b0r, b0i, (TREE && f == fc) ? 1 : 0, n, m, ur, ui, col, nullptr);
     double dre = res.dre, dim = res.dim;
     if (TREE && f == fc) {
       const uint32_t crow = global_row(p.src_rowoff[(size_t)x.i * p.sn + o + rc], p.M);
       if (res.zero) {
-        block_det_direct<GROUP, NMAX>(base, myrow, rc, crow, co, n, m, dre, dim, nullptr);
+        block_det_direct<GROUP, NMAX>(base, myrow, rc, crow, co, n, m, dre, dim);
       } else {
-        double x_r, x_i;
-        replay_unit<GROUP, NMAX, false>(ar, ai, piv, rc, n, m, ur, ui, x_r, x_i, nullptr);
+        // x = G^-1 e_r: x[col_m] = b'[m] / u_m
+        const double x_r = b0r[0] * ur - b0i[0] * ui;
+        const double x_i = b0r[0] * ui + b0i[0] * ur;
         uint32_t mycol = 0;
 #pragma unroll
         for (int c = 0; c < NMAX; ++c)
@@ -235,7 +238,7 @@ hipError_t launch_pairs(const PairArgs& a, int n, bool narrow, bool tree, int pi
       default: return hipErrorInvalidValue;
     }
   }
-  if (n <= 8) return launch_group<16, 8>(a, tree, s);
+  if (n <= 8) return launch_group<8, 8>(a, tree, s);
   if (n <= 12) return launch_group<16, 12>(a, tree, s);
   if (n <= 16) return launch_group<16, 16>(a, tree, s);
   if (n <= 18) return launch_group<32, 18>(a, tree, s);
