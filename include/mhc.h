@@ -72,6 +72,16 @@ enum { MHC_TREE_NO_SHARING = 0x100 };
  * a term whose owner was dropped moves to the kept dominator of its closed
  * neighbourhood that was picked first. */
 enum { MHC_TREE_PRUNE = 0x200 };
+/* Flag or-ed into the policy of mhc_tree_build: edges between terms whose
+ * flavour blocks, taken as sets of indices, differ in exactly one element
+ * (Sec. 3 links matrices that differ by a single row without fixing the
+ * order of the rows; an ablation).  A child's matrix is then a row
+ * permutation of its dominator's with one row replaced: its determinant is
+ * the permutation's sign times the updated one.  Positional neighbours are
+ * set neighbours with sign +1.  Forward contraction only (one-sided tree and
+ * plain methods, mhc_contract and the batch); the adjoint and the two-sided
+ * method refuse such trees (MHC_E_UNSUPPORTED). */
+enum { MHC_TREE_SET_EDGES = 0x400 };
 
 /* Contraction methods. */
 enum {
@@ -91,7 +101,15 @@ enum {
    * candidates (growth per step at most 11), so exchanges are rare.  Every
    * block must have one size n <= 8. */
   MHC_PLAIN_LU_THRESHOLD = 5,
-  MHC_UPDATE_TREE_THRESHOLD = 6
+  MHC_UPDATE_TREE_THRESHOLD = 6,
+  /* The update tree with weighted-row aggregation (an extension of the
+   * sharing of Sec. 2): the determinant is multilinear in row r, so the
+   * children of a group, which replace the same row r, contribute
+   * det G * ((sum_c w_c s_c) . x_r): one dot per group instead of one per
+   * child.  No child's own ratio is formed, so A and the dense pair_det
+   * form must be NULL; sampled pairs are evaluated as by the update
+   * tree. */
+  MHC_UPDATE_TREE_AGG = 7
 };
 
 typedef struct mhc_terms mhc_terms;
@@ -133,7 +151,7 @@ mhc_status mhc_terms_shape(const mhc_terms* terms, int32_t* n_terms,
  * e_r v^T).  The greedy rule `policy` (MHC_GREEDY_R1 or R2, optionally
  * | MHC_TREE_NO_SHARING and/or | MHC_TREE_PRUNE) picks dominators; every
  * other term becomes a child of the first dominator whose neighbourhood
- * covered it.
+ * covered it (with MHC_TREE_SET_EDGES the neighbourhood is taken on sets).
  * Host only; depends on neither S nor the weights, so one tree serves every
  * gauge configuration and time slice. */
 mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
@@ -149,6 +167,12 @@ mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
 mhc_status mhc_tree_export(const mhc_tree* tree, int32_t* n_dom,
                            int32_t* dom_order, int32_t* owner, int32_t* flav,
                            int32_t* pos);
+/* Per term (host arrays of n_terms int32 each, either may be NULL): the new
+ * index in the row that differs from its dominator (Sec. 2: the row s of
+ * the update) and the sign of the row permutation between the child's
+ * blocks and the dominator's with that row replaced (1 for positional
+ * edges); -1 and 0 for dominators.  Errors: MHC_E_ARG (NULL tree). */
+mhc_status mhc_tree_children(const mhc_tree* tree, int32_t* new_index, int32_t* sign);
 /* Counts of the tree (any pointer may be NULL): dominators (Sec. 3: the
  * matrices that get a full factorisation), (dominator, flavour, row)
  * groups (Sec. 2: children that change the same row of a dominator share
@@ -212,15 +236,17 @@ void mhc_plan_destroy(mhc_plan* plan);
  * floating-point rounding: MHC_PLAIN_LU, MHC_UPDATE_TREE (the paper's
  * method), MHC_UPDATE_TREE2 (needs an attached sink tree, computes neither
  * A nor pair_det: both must be NULL), the unpivoted ablations and the
- * threshold-pivoting variants (blocks of one size n <= 8).  Every pointer
+ * threshold-pivoting variants (blocks of one size n <= 8) and
+ * MHC_UPDATE_TREE_AGG (no A, no dense pair_det).  Every pointer
  * must stay valid until the stream has run the work.  The plan holds the
  * workgroup partial sums: two contractions on one plan that overlap in
  * time (on different streams) race; a call that needs a larger partial
  * buffer than any before waits for the device, then grows it.
  * Errors: MHC_E_ARG (NULL plan or buffer, T or n_pairs out of range, pairs
  * without pair_det), MHC_E_STATE (MHC_UPDATE_TREE2 without a sink tree),
- * MHC_E_UNSUPPORTED (method not available for these blocks, pair_det with
- * more than 4 blocks), MHC_E_DEVICE, MHC_E_OOM. */
+ * MHC_E_UNSUPPORTED (method not available for these blocks or trees,
+ * pair_det with more than 4 blocks, A or dense pair_det with
+ * MHC_UPDATE_TREE_AGG), MHC_E_DEVICE, MHC_E_OOM. */
 mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
                         const void* S, const double* w_src,
                         const double* w_snk, void* C, double* A,

@@ -24,6 +24,12 @@ Readings taken here (the paper leaves them open):
   counted in the graph induced on the remaining vertices (lowest index on
   ties), and the chosen vertex and its remaining neighbours are removed.
   The dominators it returns are pairwise non-adjacent.
+* "set" edges (an ablation; Sec. 3 speaks of matrices that differ by a
+  single row without fixing the row order): two terms are neighbours when
+  their flavour blocks, taken as sets of indices, differ in exactly one
+  element.  A child's matrix is then a row permutation of its dominator's
+  with one row replaced, so its determinant carries the sign of that
+  permutation.
 * "prune" (optional, after either rule): Sec. 3 names a better
   dominating-set approximation as the first improvement.  Here that is the
   classic reverse-delete pass: dominators are visited in reverse pick order
@@ -61,13 +67,89 @@ def hamming1_pairs(terms, chunk=256):
     return np.concatenate(out).astype(np.int64)
 
 
-def adjacency(terms) -> sp.csr_matrix:
+def adjacency(terms, nf=None, edges="position") -> sp.csr_matrix:
+    """Neighbour graph: positional Hamming distance 1 (default) or, with
+    edges="set", set distance 1 (set1_pairs; needs nf)."""
     n = len(terms)
-    e = hamming1_pairs(terms)
+    e = hamming1_pairs(terms) if edges == "position" else set1_pairs(terms, nf)
     data = np.ones(2 * len(e), dtype=np.int64)
     rows = np.concatenate([e[:, 0], e[:, 1]])
     cols = np.concatenate([e[:, 1], e[:, 0]])
     return sp.csr_matrix((data, (rows, cols)), shape=(n, n))
+
+
+def set_distance(a, b, nf) -> int:
+    """Sec. 3 edges read as sets (the set-edge ablation): the number of
+    elements of a's flavour blocks that b's blocks lack (blocks of equal
+    size, indices distinct within a block)."""
+    offs = np.concatenate([[0], np.cumsum(nf)]).astype(int)
+    return sum(len(set(np.asarray(a)[offs[f]:offs[f + 1]].tolist())
+                   - set(np.asarray(b)[offs[f]:offs[f + 1]].tolist()))
+               for f in range(len(nf)))
+
+
+def set1_pairs(terms, nf, chunk=128):
+    """All (i, j), i < j, at set distance exactly 1 (one flavour block
+    differs in one element, every other block holds the same indices), by
+    comparing every pair: for each block, the elements of i's block found
+    anywhere in j's block are counted.  Returns int64 [E][2]."""
+    terms = np.asarray(terms)
+    n = len(terms)
+    offs = np.concatenate([[0], np.cumsum(nf)]).astype(int)
+    out = []
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        missing = np.zeros((hi - lo, n), dtype=np.int64)
+        for f in range(len(nf)):
+            a = terms[lo:hi, offs[f]:offs[f + 1]]          # [c][n_f]
+            b = terms[:, offs[f]:offs[f + 1]]              # [N][n_f]
+            found = (a[:, :, None, None] == b[None, None, :, :]).any(axis=3)   # [c][n_f][N]
+            missing += nf[f] - found.sum(axis=1)
+        ii, jj = np.nonzero(missing == 1)
+        ii = ii + lo
+        keep = ii < jj
+        out.append(np.stack([ii[keep], jj[keep]], axis=1))
+    if not out:
+        return np.zeros((0, 2), dtype=np.int64)
+    return np.concatenate(out).astype(np.int64)
+
+
+def permutation_sign(src, dst) -> int:
+    """Sign of the permutation that reorders the distinct values src into
+    dst (dst[m] = src[p(m)]), by counting inversions of p."""
+    where = {v: k for k, v in enumerate(src)}
+    p = [where[v] for v in dst]
+    inv = sum(1 for x in range(len(p)) for y in range(x + 1, len(p)) if p[x] > p[y])
+    return -1 if inv % 2 else 1
+
+
+def set_child(dom, child, nf):
+    """For terms at set distance 1: (flavour f, row r of the dominator's
+    block f that is replaced, the new index, sign).  With b the dominator's
+    tuple with row r of block f replaced by the new index, every block of
+    the child holds the indices of b's block in some order, so G of the
+    child is a row permutation of G with b's rows, and its determinant is
+    sign * det(b's G) (Sec. 2: b's block f is the dominator's with one row
+    changed)."""
+    offs = np.concatenate([[0], np.cumsum(nf)]).astype(int)
+    dom = [int(v) for v in dom]
+    child = [int(v) for v in child]
+    fc = r = new = None
+    for f in range(len(nf)):
+        bd, bu = dom[offs[f]:offs[f + 1]], child[offs[f]:offs[f + 1]]
+        gone = [v for v in bd if v not in bu]
+        if gone:
+            assert len(gone) == 1 and fc is None, "not at set distance 1"
+            fc, r = f, bd.index(gone[0])
+            new = [v for v in bu if v not in bd][0]
+    assert fc is not None, "not at set distance 1"
+    sign = 1
+    for f in range(len(nf)):
+        b = dom[offs[f]:offs[f + 1]]
+        if f == fc:
+            b[r] = new
+        sign *= permutation_sign(b, child[offs[f]:offs[f + 1]])
+    return fc, r, new, sign
 
 
 def differing_position(a, b) -> int:
@@ -141,32 +223,38 @@ def prune(dom_order, owner, adj):
     return order, new_owner
 
 
-def build(terms, nf, policy=R2, prune_set=False):
+def build(terms, nf, policy=R2, prune_set=False, edges="position"):
     """Tree arrays in the library's export format.
 
     Returns dict with n_dom, dom_order (int32[N], -1 past n_dom), owner,
-    flav, pos (int32[N]; flav = pos = -1 for dominators)."""
+    flav, pos (int32[N]; flav = pos = -1 for dominators), and per child the
+    new index of its changed row and the sign of its row permutation
+    (new = -1, sign = 0 for dominators; sign 1 for positional edges)."""
     terms = np.asarray(terms)
     n = len(terms)
-    adj = adjacency(terms)
+    adj = adjacency(terms, nf, edges)
     dom_order, owner = greedy(terms, policy, adj)
     if prune_set:
         dom_order, owner = prune(dom_order, owner, adj)
     offs = np.concatenate([[0], np.cumsum(nf)]).astype(int)
     flav = np.full(n, -1, dtype=np.int32)
     pos = np.full(n, -1, dtype=np.int32)
+    new = np.full(n, -1, dtype=np.int32)
+    sign = np.zeros(n, dtype=np.int32)
     for u in range(n):
         d = int(owner[u])
         if d == u:
             continue
-        p = differing_position(terms[u], terms[d])
-        f = int(np.searchsorted(offs, p, side="right") - 1)
-        flav[u] = f
-        pos[u] = p - offs[f]
+        if edges == "position":
+            p = differing_position(terms[u], terms[d])
+            f = int(np.searchsorted(offs, p, side="right") - 1)
+            flav[u], pos[u], new[u], sign[u] = f, p - offs[f], terms[u][p], 1
+        else:
+            flav[u], pos[u], new[u], sign[u] = set_child(terms[d], terms[u], nf)
     order = np.full(n, -1, dtype=np.int32)
     order[:len(dom_order)] = dom_order
     return dict(n_dom=len(dom_order), dom_order=order,
-                owner=owner.astype(np.int32), flav=flav, pos=pos)
+                owner=owner.astype(np.int32), flav=flav, pos=pos, new=new, sign=sign)
 
 
 def groups(tree):

@@ -29,8 +29,10 @@ PLAIN_LU_UNPIVOTED = 3
 UPDATE_TREE_UNPIVOTED = 4
 PLAIN_LU_THRESHOLD = 5
 UPDATE_TREE_THRESHOLD = 6
+UPDATE_TREE_AGG = 7
 TREE_NO_SHARING = 0x100
 TREE_PRUNE = 0x200
+TREE_SET_EDGES = 0x400
 SCHED_AUTO = 0
 SCHED_LANE = 1
 SCHED_GROUP = 2
@@ -60,6 +62,7 @@ SIGNATURES = {
     "mhc_tree_export": (_I32, [_P, _PI32, _PI32, _PI32, _PI32, _PI32]),
     "mhc_tree_stats": (_I32, [_P, _PI32, _PI32, _PI32]),
     "mhc_tree_groups": (_I32, [_P, _PI32, _PI32, _PI32, _PI32, _PI32]),
+    "mhc_tree_children": (_I32, [_P, _PI32, _PI32]),
     "mhc_tree_destroy": (None, [_P]),
     "mhc_plan_create": (_I32, [_P, _P, _P, ctypes.POINTER(_P)]),
     "mhc_plan_destroy": (None, [_P]),

@@ -20,13 +20,17 @@ struct PlanView {
   const int32_t* grp_ptr;         // [n_groups+1] child range of each group
   const uint32_t* child_rowoff;   // [n_children] byte offset of the new row
   const int32_t* child_term;      // [n_children] source term of the child
+  const double* child_wsgn;       // [n_children] sign of the child's row
+                                  // permutation (+1 with positional edges)
   // plain method: every source term is its own row set
   const uint32_t* src_rowoff;     // [n_src][sn]
-  // per source term: its dominator's term id (itself for a dominator) and
-  // the (flavour << 8) | row in which it differs from it (-1 for a
-  // dominator); read by the per-pair kernels only
+  // per source term: its dominator's term id (itself for a dominator), the
+  // (flavour << 8) | row in which it differs from it, plus 1 << 16 where
+  // its row permutation is odd (-1 for a dominator), and the byte offset of
+  // its new row; read by the per-pair kernels only
   const int32_t* term_owner;      // [n_src]
   const int32_t* term_fr;         // [n_src]
+  const uint32_t* term_crow;      // [n_src]
   // sinks, position-major for coalesced loads; padded sinks repeat sink 0
   const uint32_t* snk_coloff;     // [sn][n_snk_pad] byte offset b*16
 };
@@ -93,7 +97,9 @@ hipError_t launch_pairs(const PairArgs& a, int n, bool narrow, bool tree, int pi
 // flavour block of size n <= 8) and the final reduction into C[T] (and A[T]
 // if non-null).  diag selects the kernels that also produce A and pair
 // determinants.  Work items are (row set, block of 64 sinks).
-// pivot: 0 none (ablation), 1 partial pivoting, 2 threshold partial pivoting.
+// pivot: 0 none (ablation), 1 partial pivoting, 2 threshold partial pivoting,
+// 3 partial pivoting with weighted-row aggregation of each group's children
+// (tree only, neither A nor pair determinants).
 hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag, int pivot,
                            double2* C, double* A, hipStream_t s);
 
@@ -101,7 +107,7 @@ hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag, i
 // any sizes up to nmax <= 24, different per flavour.  Work items are
 // (row set, block of wide_sinks_per_wave(nmax) sinks).
 hipError_t launch_contract_wide(const ContractArgs& a, int nmax, bool tree, bool diag,
-                                double2* C, double* A, hipStream_t s);
+                                double2* C, double* A, hipStream_t s, bool agg = false);
 int wide_sinks_per_wave(int nmax);
 
 // Two-sided update trees (one matrix per lane, every block of size n <= 8):
@@ -119,6 +125,9 @@ hipError_t launch_batch_lane(const BatchArgs& b, int n, bool tree, bool with_a, 
 hipError_t launch_batch_wide(const BatchArgs& b, int nmax, bool tree, bool with_a, int grid,
                              size_t lds, hipStream_t s);
 int wide_bucket(int nmax);
+// Workgroups of a bucket's persistent batch kernel that stay resident on
+// one compute unit together, for the LDS bytes one slice of S takes.
+int batch_wide_resident(int nmax, bool tree, bool with_a, size_t lds);
 // Threads per workgroup of a group kernel (512 or 1024) for a bucket and
 // the LDS bytes one slice of S takes.
 int wide_block(int nmax, bool tree, size_t lds);

@@ -65,7 +65,9 @@ __device__ __forceinline__ void child_det_direct(const char* lds,
 }
 
 // MODE bit 0: accumulate A(t) = sum |w w d|; bit 1: write every pair det;
-// bit 2: no pivoting (ablation); bit 3: threshold partial pivoting.
+// bit 2: no pivoting (ablation); bit 3: threshold partial pivoting; bit 4:
+// weighted-row aggregation (the children of a group enter through one dot
+// product of their weighted rows, so no child's own ratio is formed).
 // One tile: slice t, the chunk-th strided share of the slice's work items.
 // The workgroup stages S_t in LDS (smem), walks its items and writes one
 // partial (re, im, A) for (t, chunk).
@@ -75,6 +77,8 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
   constexpr bool WITH_A = (MODE & 1) != 0;
   constexpr int PIV = (MODE & 4) ? kNoPivot : (MODE & 8) ? kThresholdPivot : kPartialPivot;
   constexpr bool WITH_PAIRS = (MODE & 2) != 0;
+  constexpr bool AGG = (MODE & 16) != 0;
+  static_assert(!AGG || (MODE & 3) == 0, "aggregation forms no per-pair values");
   const PlanView& p = a.plan;
   __syncthreads();  // the previous tile of this workgroup is done with LDS
   const int lane = threadIdx.x & (kWave - 1);
@@ -171,6 +175,37 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
           const int c_begin = uniform(p.grp_ptr[gg]);
           const int c_end = uniform(p.grp_ptr[gg + 1]);
           solve_unit_col<N>(gr, gi, r, gg, [&](const double (&xr)[N], const double (&xi)[N]) {
+            if constexpr (AGG) {
+              // multilinearity in row r: sum_c w_c det(G, row r := s_c) =
+              // det(G, row r := sum_c w_c s_c), so the weighted rows are
+              // summed first and dotted with x once
+              double hr[N], hi[N];
+#pragma unroll
+              for (int n = 0; n < N; ++n) {
+                hr[n] = 0.0;
+                hi[n] = 0.0;
+              }
+              for (int c = c_begin; c < c_end; ++c) {
+                const uint32_t crow = uniform(p.child_rowoff[c]);
+                const double wc = a.w_src[uniform(p.child_term[c])] * p.child_wsgn[c];
+                double2 sv[N];
+#pragma unroll
+                for (int n = 0; n < N; ++n)
+                  sv[n] = *reinterpret_cast<const double2*>(lds + crow + co[n]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int n = 0; n < N; ++n) {
+                  hr[n] = hr[n] + wc * sv[n].x;
+                  hi[n] = hi[n] + wc * sv[n].y;
+                }
+              }
+#pragma unroll
+              for (int n = 0; n < N; ++n) {
+                sre = sre + hr[n] * xr[n] - hi[n] * xi[n];
+                sim = sim + hr[n] * xi[n] + hi[n] * xr[n];
+              }
+              return;
+            }
             for (int c = c_begin; c < c_end; ++c) {
               const uint32_t crow = uniform(p.child_rowoff[c]);
               const int cterm = uniform(p.child_term[c]);
@@ -188,12 +223,14 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
                 rr = rr + sv[n].x * xr[n] - sv[n].y * xi[n];
                 ri = ri + sv[n].x * xi[n] + sv[n].y * xr[n];
               }
-              const double wc = a.w_src[cterm];
+              // the child's weight carries the sign of its row permutation
+              const double sg = p.child_wsgn[c];
+              const double wc = a.w_src[cterm] * sg;
               sre += wc * rr;
               sim += wc * ri;
               if (WITH_A && !zero) sabs_reg += fabs(wc) * cabs_scaled(rr, ri);
               if (WITH_PAIRS && valid && a.pair_det && !zero) {
-                double cr = rr * dre - ri * dim, ci = rr * dim + ri * dre;
+                double cr = sg * (rr * dre - ri * dim), ci = sg * (rr * dim + ri * dre);
 #pragma unroll
                 for (int q = 0; q < kPairFlavors; ++q) {
                   if (q == f || q >= F) continue;
@@ -257,6 +294,8 @@ __device__ __forceinline__ void lane_tile(const ContractArgs& a, int t, int chun
               if (need && fbad == f) {
                 double cre, cim;
                 child_det_direct<N>(lds, rowoff_d + o, r, p.child_rowoff[c], co, cre, cim);
+                cre *= p.child_wsgn[c];
+                cim *= p.child_wsgn[c];
                 const double wc = a.w_src[p.child_term[c]];
                 fre += wc * cre;
                 fim += wc * cim;
@@ -382,6 +421,7 @@ static hipError_t launch_one(const ContractArgs& a, hipStream_t s) {
 template <int N>
 static hipError_t launch_n(const ContractArgs& a, bool tree, bool diag, int pivot,
                            hipStream_t s) {
+  if (pivot == 3) return launch_one<N, true, 16>(a, s);   // weighted-row aggregation
   if (pivot == 2) {
     if (tree) return diag ? launch_one<N, true, 11>(a, s) : launch_one<N, true, 8>(a, s);
     return diag ? launch_one<N, false, 11>(a, s) : launch_one<N, false, 8>(a, s);

@@ -125,11 +125,23 @@ constexpr int prow_entries() {
 // prow_entries complex entries: the row from column k on, then the
 // right-hand sides) and every lane reads it back; otherwise every entry
 // moves by a ds_bpermute shuffle.
-template <int GROUP, int NMAX, int RMAX, bool LDS_BCAST>
+// Pivot lanes of the elimination steps, 5 bits each.
+template <int NMAX>
+struct PivotLanes {
+  uint32_t w[(NMAX + 5) / 6];
+  __device__ __forceinline__ int get(int k) const { return (w[k / 6] >> (5 * (k % 6))) & 31; }
+};
+
+// KEEP: each row also keeps its multiplier l_m of step k in its column k
+// (which the step no longer needs) and piv records the pivot lane of every
+// step, so that replay_units can apply the same row operations to unit
+// columns afterwards.
+template <int GROUP, int NMAX, int RMAX, bool LDS_BCAST, bool KEEP = false>
 __device__ __forceinline__ GJResult gauss_jordan_rhs(double (&ar)[NMAX], double (&ai)[NMAX],
                                                      double (&br)[RMAX], double (&bi)[RMAX],
                                                      int nr, int n, int m, double& ur,
-                                                     double& ui, int& col, double2* prow) {
+                                                     double& ui, int& col, double2* prow,
+                                                     PivotLanes<NMAX>* piv = nullptr) {
   static_assert(GROUP <= 32, "lane rank is packed into 5 bits");
   GJResult res{1.0, 0.0, false};
   bool done = m >= n;
@@ -138,6 +150,7 @@ __device__ __forceinline__ GJResult gauss_jordan_rhs(double (&ar)[NMAX], double 
   ur = 0.0;
   ui = 0.0;
   col = -1;
+  if constexpr (KEEP) static_for<0, (NMAX + 5) / 6>([&](auto ic) { piv->w[decltype(ic)::value] = 0u; });
   static_for<0, NMAX>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     if (k >= n) return;
@@ -149,6 +162,7 @@ __device__ __forceinline__ GJResult gauss_jordan_rhs(double (&ar)[NMAX], double 
     // (some row of the group is always unused at step k < n, so the max
     // carries a rank 0 <= p < GROUP; the mask only keeps the lane in range)
     const int p = (31 - (int)(__double2loint(key) & 31u)) & (GROUP - 1);
+    if constexpr (KEEP) piv->w[k / 6] |= (uint32_t)p << (5 * (k % 6));
     // sign: rows below p that are still unused each contribute one
     // transposition to the pivot permutation
     const uint64_t open = __builtin_amdgcn_ballot_w64(!done);
@@ -231,12 +245,67 @@ __device__ __forceinline__ GJResult gauss_jordan_rhs(double (&ar)[NMAX], double 
       if constexpr (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
     });
     if constexpr (LDS_BCAST) wave_lds_sync();   // the row is read before the next step writes
+    if constexpr (KEEP) {
+      if (!me) {
+        ar[k] = lr;
+        ai[k] = li;
+      }
+    }
   });
   if (neg) {
     res.dre = -res.dre;
     res.dim = -res.dim;
   }
   return res;
+}
+
+// Applies the row operations of gauss_jordan_rhs<..., KEEP> to nr <= RMAX
+// columns b_q at once (lane m holds entry m of each; on entry the unit
+// columns e_{r_q}): step k subtracts l_m(k) times the pivot lane's entries.
+// On return the system reads u_m x[col_m] = b'_q[m], as if the columns had
+// been carried through the elimination.  One pass serves every column, so
+// the chain of broadcasts is paid once, not once per column.  The pivot
+// lane's entries go through the group's LDS buffer (its first nr entries;
+// the elimination no longer needs it) or through shuffles.
+template <int GROUP, int NMAX, int RMAX, bool LDS_BCAST>
+__device__ __forceinline__ void replay_units(const double (&ar)[NMAX], const double (&ai)[NMAX],
+                                             const PivotLanes<NMAX>& piv, int n, int m,
+                                             double (&br)[RMAX], double (&bi)[RMAX], int nr,
+                                             double2* prow) {
+  const int gbase = (__lane_id() / GROUP) * GROUP;
+  static_for<0, NMAX>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if (k >= n) return;
+    const int p = piv.get(k);
+    const bool upd = m != p && m < n;
+    if constexpr (LDS_BCAST) {
+      if (m == p) {
+        static_for<0, RMAX>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          if (q < nr) prow[q] = make_double2(br[q], bi[q]);
+        });
+      }
+      wave_lds_sync();
+    }
+    static_for<0, RMAX>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      if (q >= nr) return;
+      double sr, si;
+      if constexpr (LDS_BCAST) {
+        const double2 b = prow[q];
+        sr = b.x;
+        si = b.y;
+      } else {
+        sr = __shfl(br[q], gbase + p, 64);
+        si = __shfl(bi[q], gbase + p, 64);
+      }
+      if (upd) {
+        br[q] = br[q] - ar[k] * sr + ai[k] * si;
+        bi[q] = bi[q] - ar[k] * si - ai[k] * sr;
+      }
+    });
+    if constexpr (LDS_BCAST) wave_lds_sync();
+  });
 }
 
 // Loads this lane's row of the block G[m][c] = S_t[row m][col c] from the

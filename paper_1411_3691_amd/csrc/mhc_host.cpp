@@ -82,6 +82,93 @@ void hamming1_graph(const mhc_terms& t, std::vector<int64_t>& ptr,
     std::copy(adj[u].begin(), adj[u].end(), nbr.begin() + ptr[u]);
 }
 
+// Set edges (an ablation of the edge rule): two terms are neighbours when
+// their flavour blocks, as sets of indices, differ in exactly one element of
+// one block.  With every block sorted, such terms share the key "block f
+// without one of its elements, every other block whole" for exactly one
+// choice of removed element on each side, and the removed elements differ
+// (equal ones would make the sets equal: distance 0, no edge).  For every
+// block f all n_f keys of every term are sorted together; inside a run of
+// equal keys, entries of two terms with different removed elements are
+// neighbours.  Each edge is found once.
+void set1_graph(const mhc_terms& t, std::vector<int64_t>& ptr, std::vector<int32_t>& nbr) {
+  const int n = t.n_terms, sn = t.sn, F = t.n_flavors;
+  std::vector<int32_t> canon(t.idx);
+  for (int u = 0; u < n; ++u)
+    for (int f = 0; f < F; ++f)
+      std::sort(canon.begin() + (int64_t)u * sn + t.off[f],
+                canon.begin() + (int64_t)u * sn + t.off[f + 1]);
+  const int32_t* C = canon.data();
+  std::vector<std::vector<int32_t>> adj(n);
+  for (int f = 0; f < F; ++f) {
+    const int nf = t.nf[f];
+    // entry = (term, position e of the removed element within block f)
+    std::vector<std::pair<int32_t, int32_t>> ent;
+    ent.reserve((size_t)n * nf);
+    for (int u = 0; u < n; ++u)
+      for (int e = 0; e < nf; ++e) ent.emplace_back(u, e);
+    // key of an entry: the sorted tuple with block f's e-th element skipped
+    auto key_at = [&](const std::pair<int32_t, int32_t>& x, int q) {
+      // q-th entry of the key (sn - 1 entries)
+      const int skip = t.off[f] + x.second;
+      return C[(int64_t)x.first * sn + (q < skip ? q : q + 1)];
+    };
+    auto less = [&](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+      for (int q = 0; q < sn - 1; ++q) {
+        const int32_t x = key_at(a, q), y = key_at(b, q);
+        if (x != y) return x < y;
+      }
+      return a < b;
+    };
+    std::sort(ent.begin(), ent.end(), less);
+    auto same = [&](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+      for (int q = 0; q < sn - 1; ++q)
+        if (key_at(a, q) != key_at(b, q)) return false;
+      return true;
+    };
+    const size_t m = ent.size();
+    for (size_t lo = 0; lo < m;) {
+      size_t hi = lo + 1;
+      while (hi < m && same(ent[lo], ent[hi])) ++hi;
+      for (size_t a = lo; a < hi; ++a)
+        for (size_t b = a + 1; b < hi; ++b) {
+          const int32_t u = ent[a].first, v = ent[b].first;
+          const int32_t xu = C[(int64_t)u * sn + t.off[f] + ent[a].second];
+          const int32_t xv = C[(int64_t)v * sn + t.off[f] + ent[b].second];
+          if (u != v && xu != xv) {
+            adj[u].push_back(v);
+            adj[v].push_back(u);
+          }
+        }
+      lo = hi;
+    }
+  }
+  ptr.assign(n + 1, 0);
+  for (int u = 0; u < n; ++u) {
+    std::sort(adj[u].begin(), adj[u].end());
+    ptr[u + 1] = ptr[u] + (int64_t)adj[u].size();
+  }
+  nbr.resize(ptr[n]);
+  for (int u = 0; u < n; ++u)
+    std::copy(adj[u].begin(), adj[u].end(), nbr.begin() + ptr[u]);
+}
+
+// Sign of the permutation p with dst[m] = src[p(m)] (distinct values), by
+// counting inversions.
+static int permutation_sign(const int32_t* src, const int32_t* dst, int k) {
+  int inv = 0;
+  int pos[kMaxPerFlavor];
+  for (int m = 0; m < k; ++m) {
+    pos[m] = 0;
+    for (int j = 0; j < k; ++j)
+      if (src[j] == dst[m]) pos[m] = j;
+  }
+  for (int x = 0; x < k; ++x)
+    for (int y = x + 1; y < k; ++y)
+      if (pos[x] > pos[y]) ++inv;
+  return (inv & 1) ? -1 : 1;
+}
+
 }  // namespace mhc
 
 using mhc::fail;
@@ -292,7 +379,8 @@ mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
   if (!src) return fail(MHC_E_ARG, "mhc_tree_build: NULL terms");
   const bool share = (policy & MHC_TREE_NO_SHARING) == 0;
   const bool prune = (policy & MHC_TREE_PRUNE) != 0;
-  policy &= ~(MHC_TREE_NO_SHARING | MHC_TREE_PRUNE);
+  const bool set_edges = (policy & MHC_TREE_SET_EDGES) != 0;
+  policy &= ~(MHC_TREE_NO_SHARING | MHC_TREE_PRUNE | MHC_TREE_SET_EDGES);
   if (policy != MHC_GREEDY_R1 && policy != MHC_GREEDY_R2)
     return fail(MHC_E_ARG, "mhc_tree_build: policy must be R1 or R2");
   mhc_tree* tr = new (std::nothrow) mhc_tree();
@@ -300,10 +388,14 @@ mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
   try {
     tr->terms = *src;
     tr->policy = policy;
+    tr->set_edges = set_edges;
     const int n = src->n_terms, sn = src->sn;
     std::vector<int64_t> ptr;
     std::vector<int32_t> nbr;
-    mhc::hamming1_graph(*src, ptr, nbr);
+    if (set_edges)
+      mhc::set1_graph(*src, ptr, nbr);
+    else
+      mhc::hamming1_graph(*src, ptr, nbr);
     tr->owner.assign(n, -1);
     if (policy == MHC_GREEDY_R2)
       greedy_r2(ptr, nbr, n, tr->dom_order, tr->owner);
@@ -320,14 +412,44 @@ mhc_status mhc_tree_build(const mhc_terms* src, int32_t policy,
         flav_of[a] = f;
         row_of[a] = a - src->off[f];
       }
+    tr->cnew.assign(n, -1);
+    tr->sign.assign(n, 0);
     for (int u = 0; u < n; ++u) {
       int d = tr->owner[u];
       if (d == u) continue;
-      int p = -1;
-      for (int q = 0; q < sn; ++q)
-        if (I[(int64_t)u * sn + q] != I[(int64_t)d * sn + q]) p = q;
-      tr->flav[u] = flav_of[p];
-      tr->pos[u] = row_of[p];
+      const int32_t* tu = I + (int64_t)u * sn;
+      const int32_t* td = I + (int64_t)d * sn;
+      if (!set_edges) {
+        int p = -1;
+        for (int q = 0; q < sn; ++q)
+          if (tu[q] != td[q]) p = q;
+        tr->flav[u] = flav_of[p];
+        tr->pos[u] = row_of[p];
+        tr->cnew[u] = tu[p];
+        tr->sign[u] = 1;
+        continue;
+      }
+      // the block whose set differs: the dominator's element missing from
+      // the child gives the row r, the child's element missing from the
+      // dominator the new index; b = the dominator with that row replaced,
+      // and every block of the child holds b's indices in some order
+      int32_t b[mhc::kMaxFlavors * mhc::kMaxPerFlavor];
+      std::copy(td, td + sn, b);
+      for (int f = 0; f < src->n_flavors; ++f) {
+        const int o = src->off[f], k = src->nf[f];
+        for (int a = 0; a < k; ++a) {
+          if (std::find(tu + o, tu + o + k, td[o + a]) != tu + o + k) continue;
+          tr->flav[u] = f;
+          tr->pos[u] = a;
+          for (int c = 0; c < k; ++c)
+            if (std::find(td + o, td + o + k, tu[o + c]) == td + o + k) tr->cnew[u] = tu[o + c];
+          b[o + a] = tr->cnew[u];
+        }
+      }
+      int sg = 1;
+      for (int f = 0; f < src->n_flavors; ++f)
+        sg *= mhc::permutation_sign(b + src->off[f], tu + src->off[f], src->nf[f]);
+      tr->sign[u] = sg;
     }
     // Group CSR.  Children are visited in ascending term order, then
     // grouped per dominator by (f, r) with a stable sort.
@@ -398,6 +520,14 @@ mhc_status mhc_tree_groups(const mhc_tree* tr, int32_t* dom_grp, int32_t* grp_f,
   put(grp_r, tr->grp_r);
   put(grp_ptr, tr->grp_ptr);
   put(grp_child, tr->grp_child);
+  return MHC_OK;
+}
+
+mhc_status mhc_tree_children(const mhc_tree* tr, int32_t* new_index, int32_t* sign) {
+  if (!tr) return fail(MHC_E_ARG, "mhc_tree_children: NULL tree");
+  const int n = tr->terms.n_terms;
+  if (new_index) std::memcpy(new_index, tr->cnew.data(), n * sizeof(int32_t));
+  if (sign) std::memcpy(sign, tr->sign.data(), n * sizeof(int32_t));
   return MHC_OK;
 }
 

@@ -36,6 +36,12 @@ struct mhc_tree {
   std::vector<int32_t> owner;        // [n]
   std::vector<int32_t> flav;         // [n]
   std::vector<int32_t> pos;          // [n]
+  bool set_edges = false;            // MHC_TREE_SET_EDGES
+  // per child: the new index of its changed row and the sign of the row
+  // permutation that brings its blocks into the dominator's order (always
+  // 1 with positional edges); -1 and 0 for dominators
+  std::vector<int32_t> cnew;         // [n]
+  std::vector<int32_t> sign;         // [n]
   // Group CSR, in dom_order: dominator k owns groups
   // [dom_grp[k], dom_grp[k+1]); group g has flavour grp_f[g], row grp_r[g]
   // and children grp_child[grp_ptr[g] .. grp_ptr[g+1]) (term indices,
@@ -50,4 +56,6 @@ namespace mhc {
 // Hamming-distance-1 graph.
 void hamming1_graph(const mhc_terms& t, std::vector<int64_t>& ptr,
                     std::vector<int32_t>& nbr);
+// The same for set edges (blocks that differ as sets in one element).
+void set1_graph(const mhc_terms& t, std::vector<int64_t>& ptr, std::vector<int32_t>& nbr);
 }  // namespace mhc

@@ -42,6 +42,7 @@ struct mhc_plan {
   void* dev_tree2 = nullptr;
   mhc::kern::SinkTreeView view_snk{};
   int32_t n_sdom = 0, n_sgroups = 0, n_schildren = 0;
+  bool set_edges = false;              // the source tree has set edges
 };
 
 // Workgroup partial sums of mhc_contract_noalloc: a file-scope device array
@@ -141,6 +142,7 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   pl->n_groups = (int32_t)tree->grp_f.size();
   pl->n_children = (int32_t)tree->grp_child.size();
   pl->snk_idx = snk->idx;
+  pl->set_edges = tree->set_edges;
 
   const int sn = src.sn;
   const uint32_t row_bytes = (uint32_t)mhc::kern::lds_row(src.M) * 16u;  // LDS row stride
@@ -155,17 +157,19 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
     grp_fr[g] = (tree->grp_f[g] << 8) | tree->grp_r[g];
   std::vector<uint32_t> child_rowoff(pl->n_children);
   std::vector<int32_t> child_term(tree->grp_child);
-  for (int g = 0; g < pl->n_groups; ++g) {
-    const int f = tree->grp_f[g], r = tree->grp_r[g];
-    for (int c = tree->grp_ptr[g]; c < tree->grp_ptr[g + 1]; ++c) {
-      const int u = tree->grp_child[c];
-      child_rowoff[c] =
-          (uint32_t)src.idx[(size_t)u * sn + src.off[f] + r] * row_bytes;
-    }
+  std::vector<double> child_wsgn(pl->n_children);
+  for (int c = 0; c < pl->n_children; ++c) {
+    const int u = tree->grp_child[c];
+    child_rowoff[c] = (uint32_t)tree->cnew[u] * row_bytes;
+    child_wsgn[c] = tree->sign[u] < 0 ? -1.0 : 1.0;
   }
   std::vector<int32_t> term_owner(tree->owner), term_fr(src.n_terms, -1);
+  std::vector<uint32_t> term_crow(src.n_terms, 0u);
   for (int u = 0; u < src.n_terms; ++u)
-    if (tree->owner[u] != u) term_fr[u] = (tree->flav[u] << 8) | tree->pos[u];
+    if (tree->owner[u] != u) {
+      term_fr[u] = (tree->flav[u] << 8) | tree->pos[u] | (tree->sign[u] < 0 ? 1 << 16 : 0);
+      term_crow[u] = (uint32_t)tree->cnew[u] * row_bytes;
+    }
   std::vector<uint32_t> src_rowoff((size_t)src.n_terms * sn);
   for (size_t q = 0; q < src_rowoff.size(); ++q)
     src_rowoff[q] = (uint32_t)src.idx[q] * row_bytes;
@@ -185,10 +189,12 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   const size_t o_grp_ptr = append(img, tree->grp_ptr);
   const size_t o_child_rowoff = append(img, child_rowoff);
   const size_t o_child_term = append(img, child_term);
+  const size_t o_child_wsgn = append(img, child_wsgn);
   const size_t o_src_rowoff = append(img, src_rowoff);
   const size_t o_snk_coloff = append(img, snk_coloff);
   const size_t o_term_owner = append(img, term_owner);
   const size_t o_term_fr = append(img, term_fr);
+  const size_t o_term_crow = append(img, term_crow);
   const size_t o_fallback = append(img, std::vector<unsigned long long>(2, 0ull));
 
   e = hipMalloc(&pl->dev_tables, img.size());
@@ -223,10 +229,12 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   v.grp_ptr = reinterpret_cast<const int32_t*>(base + o_grp_ptr);
   v.child_rowoff = reinterpret_cast<const uint32_t*>(base + o_child_rowoff);
   v.child_term = reinterpret_cast<const int32_t*>(base + o_child_term);
+  v.child_wsgn = reinterpret_cast<const double*>(base + o_child_wsgn);
   v.src_rowoff = reinterpret_cast<const uint32_t*>(base + o_src_rowoff);
   v.snk_coloff = reinterpret_cast<const uint32_t*>(base + o_snk_coloff);
   v.term_owner = reinterpret_cast<const int32_t*>(base + o_term_owner);
   v.term_fr = reinterpret_cast<const int32_t*>(base + o_term_fr);
+  v.term_crow = reinterpret_cast<const uint32_t*>(base + o_term_crow);
   pl->fallback = reinterpret_cast<unsigned long long*>(base + o_fallback);
   pl->singular = pl->fallback + 1;
   *out = pl;
@@ -258,6 +266,9 @@ mhc_status mhc_plan_attach_sink_tree(mhc_plan* pl, const mhc_tree* st, void* str
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_plan_attach_sink_tree: two-sided trees need every flavour block of "
                 "size n <= 8");
+  if (st->set_edges)
+    return fail(MHC_E_UNSUPPORTED,
+                "mhc_plan_attach_sink_tree: two-sided trees need positional edges");
   int cur = -1;
   hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e, "mhc_plan_attach_sink_tree/hipGetDevice");
@@ -358,8 +369,13 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
     return fail(MHC_E_ARG, "mhc_contract: NULL buffer");
   if (T < 1) return fail(MHC_E_ARG, "mhc_contract: T < 1");
   if (T > 65535) return fail(MHC_E_ARG, "mhc_contract: T > 65535");
-  if (method < MHC_PLAIN_LU || method > MHC_UPDATE_TREE_THRESHOLD)
+  if (method < MHC_PLAIN_LU || method > MHC_UPDATE_TREE_AGG)
     return fail(MHC_E_ARG, "mhc_contract: unknown method");
+  const bool agg = method == MHC_UPDATE_TREE_AGG;
+  if (agg && (A || (pair_det && !pairs)))
+    return fail(MHC_E_UNSUPPORTED,
+                "mhc_contract: the weighted-row aggregation forms no per-pair values (A and "
+                "the dense pair_det must be NULL; sampled pairs are evaluated by the tree)");
   const int pivot = (method == MHC_PLAIN_LU_UNPIVOTED || method == MHC_UPDATE_TREE_UNPIVOTED) ? 0
                     : (method == MHC_PLAIN_LU_THRESHOLD || method == MHC_UPDATE_TREE_THRESHOLD)
                         ? 2
@@ -369,6 +385,10 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
                 "mhc_contract: the unpivoted and threshold-pivoting methods need every flavour "
                 "block of size n <= 8");
   if (method == MHC_UPDATE_TREE2) {
+    if (pl->set_edges)
+      return fail(MHC_E_UNSUPPORTED,
+                  "mhc_contract: the two-sided method needs positional edges (the source "
+                  "tree was built with MHC_TREE_SET_EDGES)");
     if (!pl->dev_tree2)
       return fail(MHC_E_STATE, "mhc_contract: no sink tree attached to the plan");
     if (A || pair_det)
@@ -393,7 +413,7 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
                 "mhc_contract: pair_det output supports at most 4 flavour blocks");
   const bool two = method == MHC_UPDATE_TREE2;
   const bool tree = method == MHC_UPDATE_TREE || method == MHC_UPDATE_TREE_UNPIVOTED ||
-                    method == MHC_UPDATE_TREE_THRESHOLD;
+                    method == MHC_UPDATE_TREE_THRESHOLD || agg;
   // the dense pair table comes from the contraction kernels themselves; a
   // sampled list from the per-pair kernels after them
   void* dense_pairs = pairs ? nullptr : pair_det;
@@ -451,11 +471,12 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
     e = mhc::kern::launch_contract_two_sided(a, pl->n, static_cast<double2*>(C),
                                              reinterpret_cast<hipStream_t>(stream));
   else if (narrow)
-    e = mhc::kern::launch_contract(a, pl->n, tree, diag, pivot, static_cast<double2*>(C), A,
+    e = mhc::kern::launch_contract(a, pl->n, tree, diag, agg ? 3 : pivot,
+                                   static_cast<double2*>(C), A,
                                    reinterpret_cast<hipStream_t>(stream));
   else
     e = mhc::kern::launch_contract_wide(a, pl->n, tree, diag, static_cast<double2*>(C), A,
-                                        reinterpret_cast<hipStream_t>(stream));
+                                        reinterpret_cast<hipStream_t>(stream), agg);
   if (e != hipSuccess) return hip_fail(e, "mhc_contract/launch");
   if (pairs && n_pairs > 0) {
     mhc::kern::PairArgs pa{};
@@ -508,6 +529,10 @@ mhc_status mhc_contract_backward(mhc_plan* pl, int32_t method, int32_t T, const 
     return fail(MHC_E_ARG, "mhc_contract_backward: T outside [1, 65535]");
   if (method != MHC_PLAIN_LU && method != MHC_UPDATE_TREE)
     return fail(MHC_E_ARG, "mhc_contract_backward: method must be MHC_PLAIN_LU or MHC_UPDATE_TREE");
+  if (method == MHC_UPDATE_TREE && pl->set_edges)
+    return fail(MHC_E_UNSUPPORTED,
+                "mhc_contract_backward: the tree adjoint needs positional edges (the source "
+                "tree was built with MHC_TREE_SET_EDGES)");
   if (pl->F > 4)
     return fail(MHC_E_UNSUPPORTED,
                 "mhc_contract_backward: more than 4 flavour blocks");
@@ -743,11 +768,12 @@ mhc_status batch_build(mhc_batch* b) {
     mhc::kern::BatchArgs ba{b->jobs_dev, tiles_dev + ranges[i].first, (int)ranges[i].second};
     int per_cu = b->sched.blocks_per_cu;
     if (per_cu <= 0) {
-      // as many workgroups per compute unit as stay resident together: one
-      // 1024-thread group kernel (its waves fill the SIMDs), else two where
-      // two copies of the slice fit in LDS
-      const bool big = !bk.narrow && mhc::kern::wide_block(bk.n, tree, bk.lds) >= 1024;
-      per_cu = (big || bk.lds > 72 * 1024) ? 1 : 2;
+      // as many workgroups per compute unit as stay resident together (the
+      // group kernels' registers and LDS decide; the lane kernels take two
+      // where two copies of the slice fit in LDS)
+      per_cu = bk.narrow ? (bk.lds > 72 * 1024 ? 1 : 2)
+                         : std::min(8, mhc::kern::batch_wide_resident(bk.n, tree, b->with_a,
+                                                                      bk.lds));
     }
     const int grid = std::max(1, std::min((int)ranges[i].second, n_cu * per_cu));
     le = bk.narrow

@@ -13,7 +13,9 @@
 //    s the child's row r (matrix determinant lemma), every other block is
 //    the dominator's; a dominator block with an exactly zero pivot has no
 //    inverse, and the child's block is then factorised directly, as in the
-//    contraction kernels.
+//    contraction kernels; with set edges the child's blocks are the
+//    dominator's (one row replaced) up to a row permutation, whose sign
+//    multiplies the result.
 
 #include <hip/hip_runtime.h>
 
@@ -70,8 +72,9 @@ __global__ __launch_bounds__(kPairBlock) void pair_lane_kernel(PairArgs a) {
   const char* base = reinterpret_cast<const char*>(a.S + (size_t)x.t * p.M * p.M);
   const int d = TREE ? p.term_owner[x.i] : x.i;
   const int fr = TREE ? p.term_fr[x.i] : -1;
-  const int fc = fr >= 0 ? fr >> 8 : -1;
+  const int fc = fr >= 0 ? (fr >> 8) & 0xff : -1;
   const int rc = fr & 0xff;
+  const double sg = (fr >= 0 && (fr >> 16) & 1) ? -1.0 : 1.0;   // odd row permutation
   double Dre = 1.0, Dim = 0.0;
   for (int f = 0; f < p.F; ++f) {
     const int o = p.off[f];
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_lane_kernel(PairArgs a) {
     bool zero;
     lu_crout<N, TREE, PIV>(base, ro, co, gr, gi, dre, dim, zero);
     if (TREE && f == fc) {
-      const uint32_t crow = global_row(p.src_rowoff[(size_t)x.i * p.sn + o + rc], p.M);
+      const uint32_t crow = global_row(p.term_crow[x.i], p.M);
       if (zero) {
         // no inverse: the child's block by direct LU
         uint32_t rc2[N], co2[N];
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_lane_kernel(PairArgs a) {
     cmul(Dre, Dim, dre, dim);
   }
   if (q < a.n_pairs)
-    a.out[q] = x.ok ? make_double2(Dre, Dim) : make_double2(NAN, NAN);
+    a.out[q] = x.ok ? make_double2(sg * Dre, sg * Dim) : make_double2(NAN, NAN);
 }
 
 // One group of GROUP lanes per matrix, one row per lane (blocks up to NMAX,
@@ -131,8 +134,9 @@ __global__ __launch_bounds__(kPairBlock) void pair_group_kernel(PairArgs a) {
   const char* base = reinterpret_cast<const char*>(a.S + (size_t)x.t * p.M * p.M);
   const int d = TREE ? p.term_owner[x.i] : x.i;
   const int fr = TREE ? p.term_fr[x.i] : -1;
-  const int fc = fr >= 0 ? fr >> 8 : -1;
+  const int fc = fr >= 0 ? (fr >> 8) & 0xff : -1;
   const int rc = fr & 0xff;
+  const double sg = (fr >= 0 && (fr >> 16) & 1) ? -1.0 : 1.0;   // odd row permutation
   double Dre = 1.0, Dim = 0.0;
   for (int f = 0; f < p.F; ++f) {
     const int o = p.off[f];
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_group_kernel(PairArgs a) {
         ar, ai, b0r, b0i, (TREE && f == fc) ? 1 : 0, n, m, ur, ui, col, nullptr);
     double dre = res.dre, dim = res.dim;
     if (TREE && f == fc) {
-      const uint32_t crow = global_row(p.src_rowoff[(size_t)x.i * p.sn + o + rc], p.M);
+      const uint32_t crow = global_row(p.term_crow[x.i], p.M);
       if (res.zero) {
         block_det_direct<GROUP, NMAX>(base, myrow, rc, crow, co, n, m, dre, dim);
       } else {
@@ -187,7 +191,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_group_kernel(PairArgs a) {
     cmul(Dre, Dim, dre, dim);
   }
   if (q < a.n_pairs && m == 0)
-    a.out[q] = x.ok ? make_double2(Dre, Dim) : make_double2(NAN, NAN);
+    a.out[q] = x.ok ? make_double2(sg * Dre, sg * Dim) : make_double2(NAN, NAN);
 }
 
 template <int N, bool TREE>

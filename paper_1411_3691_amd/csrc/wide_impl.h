@@ -44,15 +44,34 @@
 namespace mhc {
 namespace kern {
 
-// Workgroup sizes: 512 threads (two waves per SIMD) or 1024 (four).
+// Workgroup sizes: 512 threads (two waves per SIMD, up to 256 VGPRs per
+// lane), 768 (three, 168) or 1024 (four, 128).
 constexpr int kWideBlock = 512;
+constexpr int kWideBlockMid = 768;
 constexpr int kWideBlockBig = 1024;
 
-// Right-hand sides carried per elimination (groups of one flavour block
-// beyond this take another elimination).
-template <int NMAX>
+// The update tree's unit columns: replayed after the elimination in one
+// batched pass (true), or carried through it as right-hand sides (false).
+constexpr bool kWideReplay = false;
+
+// Right-hand sides carried per elimination by the update tree (groups of
+// one flavour block beyond this take another elimination); the plain LU
+// carries none.
+template <int NMAX, bool TREE>
 constexpr int wide_rmax() {
-  return NMAX < 8 ? NMAX : 8;
+  return !TREE ? 0 : NMAX < 8 ? NMAX : 8;
+}
+
+// Threads per workgroup of a bucket's kernel, from the registers each
+// needs: the diagnostic modes (A, pair determinants) and the tree's blocks
+// above 12 keep 512; the fast tree up to 12 runs 768 (measured faster than
+// 1024 and 512 on the large workload and the batch); the plain LU up to 12
+// and 18 fits 1024, the plain LU of 16 and 24 fits 768.
+template <int NMAX, bool TREE, int MODE>
+constexpr int wide_wb() {
+  if ((MODE & 3) != 0) return kWideBlock;
+  if (!TREE) return (NMAX == 16 || NMAX == 24) ? kWideBlockMid : kWideBlockBig;
+  return NMAX <= 12 ? kWideBlockMid : kWideBlock;
 }
 
 // The LDS a workgroup can have: 160 KiB, less 1 KiB for the static arrays
@@ -60,9 +79,11 @@ constexpr int wide_rmax() {
 constexpr size_t kWideLdsLimit = 159 * 1024;
 
 // Bytes of the groups' row buffers of one workgroup (LDS broadcasts).
-template <int GROUP, int NMAX>
+template <int GROUP, int NMAX, bool TREE>
 constexpr size_t wide_rows_bytes(int wb) {
-  return (size_t)(wb / GROUP) * prow_entries<NMAX, wide_rmax<NMAX>()>() * 16;
+  // a replay reuses the row buffer (nr <= RMAX <= NMAX entries)
+  return (size_t)(wb / GROUP) *
+         prow_entries<NMAX, kWideReplay ? 0 : wide_rmax<NMAX, TREE>()>() * 16;
 }
 
 // One tile (slice t, chunk) of a job, as lane_tile for one matrix per lane.
@@ -73,9 +94,11 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
                                           double2* smem) {
   constexpr bool WITH_A = (MODE & 1) != 0;
   constexpr bool WITH_PAIRS = (MODE & 2) != 0;
-  constexpr bool DIAG = MODE != 0;     // per-child ratios summed over the group
+  constexpr bool DIAG = (MODE & 3) != 0;   // per-child ratios summed over the group
+  constexpr bool AGG = (MODE & 16) != 0;   // weighted-row aggregation per group
+  static_assert(!(AGG && DIAG), "aggregation forms no per-pair values");
   constexpr int SPW = kWave / GROUP;   // sinks per wave
-  constexpr int RMAX = wide_rmax<NMAX>();
+  constexpr int RMAX = wide_rmax<NMAX, TREE>() > 0 ? wide_rmax<NMAX, TREE>() : 1;
   const PlanView& p = a.plan;
   __syncthreads();  // the previous tile of this workgroup is done with LDS
   const int lane = threadIdx.x & (kWave - 1);
@@ -86,8 +109,9 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
   const double2* St = a.S + (size_t)t * MM;
   constexpr int kWaves = WB / kWave;
   // this group's row buffer (LDS broadcasts only), then the copy of S_t
-  double2* prow = smem + (threadIdx.x / GROUP) * prow_entries<NMAX, RMAX>();
-  double2* slice = smem + (BCAST ? wide_rows_bytes<GROUP, NMAX>(WB) / 16 : 0);
+  double2* prow = smem + (threadIdx.x / GROUP) *
+                           prow_entries<NMAX, kWideReplay ? 0 : wide_rmax<NMAX, TREE>()>();
+  double2* slice = smem + (BCAST ? wide_rows_bytes<GROUP, NMAX, TREE>(WB) / 16 : 0);
   stage_slice(St, slice, p.M, WB);
   __syncthreads();
   const char* lds = reinterpret_cast<const char*>(slice);
@@ -197,17 +221,23 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
         }
         double ur, ui;
         int col;
-        const GJResult res = gauss_jordan_rhs<GROUP, NMAX, RMAX, BCAST>(
-            ar, ai, brr, bri, nr, n, m, ur, ui, col, prow);
+        constexpr bool REPLAY = kWideReplay && TREE;
+        PivotLanes<NMAX> piv;
+        const GJResult res = gauss_jordan_rhs<GROUP, NMAX, RMAX, BCAST, REPLAY>(
+            ar, ai, brr, bri, REPLAY ? 0 : nr, n, m, ur, ui, col, prow, &piv);
+        if (REPLAY && !direct && !res.zero && nr > 0)
+          replay_units<GROUP, NMAX, RMAX, BCAST>(ar, ai, piv, n, m, brr, bri, nr, prow);
         if (direct) {
           // the child's block determinant (its other blocks are the
-          // dominator's; the product is formed after the flavour loop)
-          const double wc = a.w_src[cterm];
+          // dominator's; the product is formed after the flavour loop),
+          // signed by its row permutation
+          const double sg = p.child_wsgn[c_first + pass - npass];
+          const double wc = a.w_src[cterm] * sg;
           bre += wc * res.dre;
           bim += wc * res.dim;
           if (WITH_A) bab += fabs(wc) * cabs_scaled(res.dre, res.dim);
           if (WITH_PAIRS && writer && a.pair_det) {
-            double cr = res.dre, ci = res.dim;
+            double cr = sg * res.dre, ci = sg * res.dim;
 #pragma unroll
             for (int h = 0; h < kPairFlavors; ++h) {
               if (h == f || h >= F) continue;
@@ -240,10 +270,29 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
           const int gg = g + g0 + q;
           const int c_begin = uniform(p.grp_ptr[gg]);
           const int c_end = uniform(p.grp_ptr[gg + 1]);
+          if constexpr (AGG) {
+            // multilinearity in row r: the children's weighted rows are
+            // summed first (this lane's column), then dotted with x once
+            double hr = 0.0, hi = 0.0;
+            for (int c = c_begin; c < c_end; ++c) {
+              const uint32_t crow = uniform(p.child_rowoff[c]);
+              const double wc = a.w_src[uniform(p.child_term[c])] * p.child_wsgn[c];
+              if (m < n) {
+                const double2 sv = *reinterpret_cast<const double2*>(lds + crow + mycol);
+                hr += wc * sv.x;
+                hi += wc * sv.y;
+              }
+            }
+            sre += hr * x_r - hi * x_i;
+            sim += hr * x_i + hi * x_r;
+            return;
+          }
           for (int c = c_begin; c < c_end; ++c) {
             const uint32_t crow = uniform(p.child_rowoff[c]);
             const int ct = uniform(p.child_term[c]);
-            const double wc = a.w_src[ct];
+            // the child's weight carries the sign of its row permutation
+            const double sg = p.child_wsgn[c];
+            const double wc = a.w_src[ct] * sg;
             double pr_ = 0.0, pi_ = 0.0;
             if (m < n) {
               const double2 s = *reinterpret_cast<const double2*>(lds + crow + mycol);
@@ -257,7 +306,7 @@ __device__ __forceinline__ void wide_tile(const ContractArgs& a, int t, int chun
               sim += wc * ri;
               if (WITH_A) sabs_reg += fabs(wc) * cabs_scaled(rr, ri);
               if (WITH_PAIRS && writer && a.pair_det) {
-                double cr = rr * dre - ri * dim, ci = rr * dim + ri * dre;
+                double cr = sg * (rr * dre - ri * dim), ci = sg * (rr * dim + ri * dre);
 #pragma unroll
                 for (int h = 0; h < kPairFlavors; ++h) {
                   if (h == f || h >= F) continue;
@@ -369,35 +418,19 @@ __global__ __launch_bounds__(WB) void batch_wide_kernel(BatchArgs b) {
   }
 }
 
-// Launch configuration of a bucket: workgroup size and whether the pivot
-// rows go through LDS, from the bytes one slice of S takes in LDS.
-struct WideConfig {
-  int wb;
-  bool bcast;
-};
-
-// 1024 threads (four waves per SIMD, 128 VGPRs per lane) for blocks up to
-// 12 in the fast mode; 512 threads (two waves, 256 VGPRs) for larger blocks
-// and for the diagnostic modes (A, pair determinants), whose per-child sums
-// and first pass over the blocks need more registers.
-template <int NMAX, int MODE>
-constexpr bool wide_big_block() {
-  return NMAX <= 12 && MODE == 0;
-}
-
+// Pivot rows through LDS where the groups' row buffers fit beside the
+// slice of S, else through shuffles.
 template <int GROUP, int NMAX, bool TREE, int MODE>
-WideConfig wide_config(size_t slice) {
-  // pivot rows through LDS where the row buffers fit beside the slice
-  const int wb = wide_big_block<NMAX, MODE>() ? kWideBlockBig : kWideBlock;
-  return {wb, slice + (wb == kWideBlockBig ? wide_rows_bytes<GROUP, NMAX>(kWideBlockBig)
-                                           : wide_rows_bytes<GROUP, NMAX>(kWideBlock)) <=
-                  kWideLdsLimit};
+bool wide_bcast(size_t slice) {
+  return slice + wide_rows_bytes<GROUP, NMAX, TREE>(wide_wb<NMAX, TREE, MODE>()) <=
+         kWideLdsLimit;
 }
 
-template <int GROUP, int NMAX, bool TREE, int MODE, int WB, bool BCAST>
+template <int GROUP, int NMAX, bool TREE, int MODE, bool BCAST>
 hipError_t launch_wide_cfg(const ContractArgs& a, size_t slice, hipStream_t s) {
+  constexpr int WB = wide_wb<NMAX, TREE, MODE>();
   dim3 grid(a.n_blk_t, a.T);
-  const size_t lds = slice + (BCAST ? wide_rows_bytes<GROUP, NMAX>(WB) : 0);
+  const size_t lds = slice + (BCAST ? wide_rows_bytes<GROUP, NMAX, TREE>(WB) : 0);
   hipError_t e = hipFuncSetAttribute(
       reinterpret_cast<const void*>(&contract_wide_kernel<GROUP, NMAX, TREE, MODE, WB, BCAST>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -410,23 +443,18 @@ hipError_t launch_wide_cfg(const ContractArgs& a, size_t slice, hipStream_t s) {
 template <int GROUP, int NMAX, bool TREE, int MODE>
 hipError_t launch_wide_one(const ContractArgs& a, hipStream_t s) {
   const size_t slice = lds_slice_bytes(a.plan.M);
-  const WideConfig c = wide_config<GROUP, NMAX, TREE, MODE>(slice);
-  if constexpr (wide_big_block<NMAX, MODE>()) {
-    if (c.bcast)
-      return launch_wide_cfg<GROUP, NMAX, TREE, MODE, kWideBlockBig, true>(a, slice, s);
-    return launch_wide_cfg<GROUP, NMAX, TREE, MODE, kWideBlockBig, false>(a, slice, s);
-  } else {
-    if (c.bcast) return launch_wide_cfg<GROUP, NMAX, TREE, MODE, kWideBlock, true>(a, slice, s);
-    return launch_wide_cfg<GROUP, NMAX, TREE, MODE, kWideBlock, false>(a, slice, s);
-  }
+  if (wide_bcast<GROUP, NMAX, TREE, MODE>(slice))
+    return launch_wide_cfg<GROUP, NMAX, TREE, MODE, true>(a, slice, s);
+  return launch_wide_cfg<GROUP, NMAX, TREE, MODE, false>(a, slice, s);
 }
 
 // diag: the scale A and/or the dense pair table; the pair table (MODE 3)
 // needs a first pass over the blocks, A alone (MODE 1) does not.
 template <int GROUP, int NMAX>
-hipError_t launch_wide_n(const ContractArgs& a, bool tree, bool diag, hipStream_t s) {
+hipError_t launch_wide_n(const ContractArgs& a, bool tree, bool diag, bool agg, hipStream_t s) {
   const bool pairs = a.pair_det != nullptr;
   if (tree) {
+    if (agg) return launch_wide_one<GROUP, NMAX, true, 16>(a, s);
     if (!diag) return launch_wide_one<GROUP, NMAX, true, 0>(a, s);
     return pairs ? launch_wide_one<GROUP, NMAX, true, 3>(a, s)
                  : launch_wide_one<GROUP, NMAX, true, 1>(a, s);
@@ -436,9 +464,10 @@ hipError_t launch_wide_n(const ContractArgs& a, bool tree, bool diag, hipStream_
                : launch_wide_one<GROUP, NMAX, false, 1>(a, s);
 }
 
-template <int GROUP, int NMAX, bool TREE, int MODE, int WB, bool BCAST>
+template <int GROUP, int NMAX, bool TREE, int MODE, bool BCAST>
 hipError_t launch_batch_wide_cfg(const BatchArgs& b, int grid, size_t slice, hipStream_t s) {
-  const size_t lds = slice + (BCAST ? wide_rows_bytes<GROUP, NMAX>(WB) : 0);
+  constexpr int WB = wide_wb<NMAX, TREE, MODE>();
+  const size_t lds = slice + (BCAST ? wide_rows_bytes<GROUP, NMAX, TREE>(WB) : 0);
   hipError_t e = hipFuncSetAttribute(
       reinterpret_cast<const void*>(&batch_wide_kernel<GROUP, NMAX, TREE, MODE, WB, BCAST>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -450,18 +479,37 @@ hipError_t launch_batch_wide_cfg(const BatchArgs& b, int grid, size_t slice, hip
 
 template <int GROUP, int NMAX, bool TREE, int MODE>
 hipError_t launch_batch_wide_m(const BatchArgs& b, int grid, size_t slice, hipStream_t s) {
-  const WideConfig c = wide_config<GROUP, NMAX, TREE, MODE>(slice);
-  if constexpr (wide_big_block<NMAX, MODE>()) {
-    if (c.bcast)
-      return launch_batch_wide_cfg<GROUP, NMAX, TREE, MODE, kWideBlockBig, true>(b, grid, slice,
-                                                                                s);
-    return launch_batch_wide_cfg<GROUP, NMAX, TREE, MODE, kWideBlockBig, false>(b, grid, slice,
-                                                                               s);
-  } else {
-    if (c.bcast)
-      return launch_batch_wide_cfg<GROUP, NMAX, TREE, MODE, kWideBlock, true>(b, grid, slice, s);
-    return launch_batch_wide_cfg<GROUP, NMAX, TREE, MODE, kWideBlock, false>(b, grid, slice, s);
-  }
+  if (wide_bcast<GROUP, NMAX, TREE, MODE>(slice))
+    return launch_batch_wide_cfg<GROUP, NMAX, TREE, MODE, true>(b, grid, slice, s);
+  return launch_batch_wide_cfg<GROUP, NMAX, TREE, MODE, false>(b, grid, slice, s);
+}
+
+// Workgroups of the batch kernel chosen for this slice size that stay
+// resident on one compute unit together (registers and LDS).
+template <int GROUP, int NMAX, bool TREE, int MODE>
+int batch_wide_resident(size_t slice) {
+  constexpr int WB = wide_wb<NMAX, TREE, MODE>();
+  const bool bc = wide_bcast<GROUP, NMAX, TREE, MODE>(slice);
+  const size_t lds = slice + (bc ? wide_rows_bytes<GROUP, NMAX, TREE>(WB) : 0);
+  const void* fn = bc ? reinterpret_cast<const void*>(
+                            &batch_wide_kernel<GROUP, NMAX, TREE, MODE, WB, true>)
+                      : reinterpret_cast<const void*>(
+                            &batch_wide_kernel<GROUP, NMAX, TREE, MODE, WB, false>);
+  int n = 0;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, WB, lds) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+template <int GROUP, int NMAX>
+int batch_wide_resident_n(bool tree, bool with_a, size_t slice) {
+  if (tree)
+    return with_a ? batch_wide_resident<GROUP, NMAX, true, 1>(slice)
+                  : batch_wide_resident<GROUP, NMAX, true, 0>(slice);
+  return with_a ? batch_wide_resident<GROUP, NMAX, false, 1>(slice)
+                : batch_wide_resident<GROUP, NMAX, false, 0>(slice);
 }
 
 template <int GROUP, int NMAX>
@@ -477,16 +525,18 @@ hipError_t launch_batch_wide_n(const BatchArgs& b, bool tree, bool with_a, int g
 // Per-bucket entry points (one translation unit each, wide_b<NMAX>.hip).
 #define MHC_WIDE_BUCKET(GROUP, NMAX)                                                        \
   hipError_t launch_contract_wide_b##NMAX(const ContractArgs& a, bool tree, bool diag,      \
-                                          hipStream_t s) {                                  \
-    return launch_wide_n<GROUP, NMAX>(a, tree, diag, s);                                    \
+                                          bool agg, hipStream_t s) {                        \
+    return launch_wide_n<GROUP, NMAX>(a, tree, diag, agg, s);                               \
   }                                                                                         \
   hipError_t launch_batch_wide_b##NMAX(const BatchArgs& b, bool tree, bool with_a, int grid, \
                                        size_t slice, hipStream_t s) {                       \
     return launch_batch_wide_n<GROUP, NMAX>(b, tree, with_a, grid, slice, s);               \
   }                                                                                         \
-  int wide_block_b##NMAX(bool tree, size_t slice) {                                         \
-    return tree ? wide_config<GROUP, NMAX, true, 0>(slice).wb                               \
-                : wide_config<GROUP, NMAX, false, 0>(slice).wb;                             \
+  int wide_block_b##NMAX(bool tree, size_t) {                                               \
+    return tree ? wide_wb<NMAX, true, 0>() : wide_wb<NMAX, false, 0>();                      \
+  }                                                                                         \
+  int batch_wide_resident_b##NMAX(bool tree, bool with_a, size_t slice) {                   \
+    return batch_wide_resident_n<GROUP, NMAX>(tree, with_a, slice);                          \
   }
 
 }  // namespace kern

@@ -26,7 +26,9 @@ METHODS = {"plain": _lib.PLAIN_LU, "tree": _lib.UPDATE_TREE, "tree2": _lib.UPDAT
            "tree_unpivoted": _lib.UPDATE_TREE_UNPIVOTED,
            # threshold partial pivoting (blocks of one size n <= 8)
            "plain_threshold": _lib.PLAIN_LU_THRESHOLD,
-           "tree_threshold": _lib.UPDATE_TREE_THRESHOLD}
+           "tree_threshold": _lib.UPDATE_TREE_THRESHOLD,
+           # weighted-row aggregation: one dot per group (no per-pair values)
+           "tree_agg": _lib.UPDATE_TREE_AGG}
 POLICIES = {"R1": _lib.GREEDY_R1, "R2": _lib.GREEDY_R2}
 
 
@@ -69,15 +71,22 @@ class Tree:
     """Update tree over source terms (host only)."""
 
     def __init__(self, terms: Terms, policy: str = "R2", share: bool = True,
-                 prune: bool = False):
+                 prune: bool = False, set_edges: bool = False):
         """share=False: every child its own group (no shared solves; an
         ablation).  prune=True: reverse-delete pass over the greedy
-        dominators (an irredundant set, never larger; Sec. 3)."""
+        dominators (an irredundant set, never larger; Sec. 3).
+        set_edges=True: terms are adjacent when their index sets differ in
+        one element per the whole term (Sec. 3 reads terms as sets of
+        rows); a child's blocks are its dominator's with one row replaced,
+        up to a row permutation whose sign multiplies the determinant
+        (forward contraction only)."""
         self.terms = terms
         self.policy = policy
         self.share = share
         self.prune = prune
-        flags = (0 if share else _lib.TREE_NO_SHARING) | (_lib.TREE_PRUNE if prune else 0)
+        self.set_edges = set_edges
+        flags = ((0 if share else _lib.TREE_NO_SHARING) | (_lib.TREE_PRUNE if prune else 0) |
+                 (_lib.TREE_SET_EDGES if set_edges else 0))
         h = ctypes.c_void_p()
         check(lib().mhc_tree_build(terms.handle, POLICIES[policy] | flags, ctypes.byref(h)))
         self._h = h
@@ -110,6 +119,16 @@ class Tree:
                                                ("dom_grp", "grp_f", "grp_r", "grp_ptr",
                                                 "grp_child"))))
         return out
+
+    def children(self):
+        """(new_index, sign) per term (mhc_tree_children): the index the
+        child's changed row takes and the sign of the row permutation to its
+        dominator's blocks; -1 and 0 for dominators."""
+        n = len(self.terms)
+        new = np.empty(n, dtype=np.int32)
+        sign = np.empty(n, dtype=np.int32)
+        check(lib().mhc_tree_children(self._h, _i32p(new), _i32p(sign)))
+        return new, sign
 
     def stats(self) -> dict:
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

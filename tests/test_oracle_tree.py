@@ -346,3 +346,93 @@ def test_groups_match_plain_regrouping_mid():
     w = W.workload("mid", T=1, n_src=600)
     t = ot.build(w.src, w.nf)
     assert ot.groups(t) == regroup_by_loops(t, w.nf)
+
+
+# ------------------------------------------------------------ set edges
+
+def permuted_terms(seed, n=70, nf=(3, 2), M=6):
+    """Random terms whose flavour blocks come in random orders."""
+    rng = np.random.default_rng(seed)
+    rows = set()
+    while len(rows) < n:
+        t = []
+        for k in nf:
+            t += [int(v) for v in rng.choice(M, k, replace=False)]
+        rows.add(tuple(t))
+    return np.array(sorted(rows))[rng.permutation(n)]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_set_pairs_brute_force(seed):
+    nf = (3, 2)
+    terms = permuted_terms(seed)
+    got = {tuple(e) for e in ot.set1_pairs(terms, nf).tolist()}
+    want = set()
+    for i in range(len(terms)):
+        for j in range(i + 1, len(terms)):
+            a, b = terms[i].tolist(), terms[j].tolist()
+            d = len(set(a[:3]) - set(b[:3])) + len(set(a[3:]) - set(b[3:]))
+            if d == 1:
+                want.add((i, j))
+    assert got == want
+    # every positional neighbour is a set neighbour
+    assert {tuple(e) for e in ot.hamming1_pairs(terms).tolist()} <= got
+
+
+def test_set_child_worked_example():
+    # dominator (0 1 2 | 3 4), child (2 5 0 | 4 3): block 0 loses 1 (row 1)
+    # and gains 5; b = (0 5 2 | 3 4); the child's blocks are b's reordered by
+    # a reversal of three (odd) and a swap (odd): sign +1
+    assert ot.set_child([0, 1, 2, 3, 4], [2, 5, 0, 4, 3], (3, 2)) == (0, 1, 5, 1)
+    # only the first block reordered by a swap: sign -1
+    assert ot.set_child([0, 1, 2, 3, 4], [5, 0, 2, 3, 4], (3, 2)) == (0, 1, 5, -1)
+    # positional change: sign +1
+    assert ot.set_child([0, 1, 2, 3, 4], [0, 1, 2, 3, 7], (3, 2)) == (1, 1, 7, 1)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_set_child_sign_by_determinants(seed):
+    # det G(child) = sign * det G(b), b the dominator with row r of block f
+    # replaced by the new index, checked with LAPACK on a random propagator
+    nf = (3, 2)
+    terms = permuted_terms(seed)
+    rng = np.random.default_rng(50 + seed)
+    S = rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6))
+    snk = [int(v) for v in rng.choice(6, 3, replace=False)] + \
+          [int(v) for v in rng.choice(6, 2, replace=False)]
+    t = ot.build(terms, nf, edges="set")
+    n_checked = 0
+    for u in range(len(terms)):
+        d = int(t["owner"][u])
+        if d == u:
+            continue
+        f, r, new, sign = (int(t["flav"][u]), int(t["pos"][u]), int(t["new"][u]),
+                           int(t["sign"][u]))
+        b = terms[d].tolist()
+        b[[0, 3][f] + r] = new
+        lhs = rhs = 1.0
+        for o, k in ((0, 3), (3, 2)):
+            lhs *= np.linalg.det(S[np.ix_(terms[u][o:o + k], snk[o:o + k])])
+            rhs *= np.linalg.det(S[np.ix_(b[o:o + k], snk[o:o + k])])
+        assert abs(lhs - sign * rhs) <= 1e-12 * max(1.0, abs(lhs)), (u, d)
+        n_checked += 1
+    assert n_checked > 0
+
+
+@pytest.mark.parametrize("policy", [ot.R1, ot.R2])
+def test_set_edges_tree_invariants(policy):
+    nf = (3, 2)
+    terms = permuted_terms(5)
+    t = ot.build(terms, nf, policy=policy, edges="set")
+    nb = [set() for _ in range(len(terms))]
+    for i, j in ot.set1_pairs(terms, nf).tolist():
+        nb[i].add(j)
+        nb[j].add(i)
+    doms = set(int(d) for d in t["dom_order"][:t["n_dom"]])
+    for u in range(len(terms)):
+        d = int(t["owner"][u])
+        assert d in doms and (d == u or d in nb[u])
+    # on permuted blocks the set graph has more edges than the positional
+    # one, so the greedy rule needs fewer dominators
+    tp = ot.build(terms, nf, policy=policy)
+    assert t["n_dom"] <= tp["n_dom"]

@@ -276,3 +276,42 @@ def test_group_tables_without_sharing(name, over):
     t = mhc.Tree(mhc.Terms(w.src, w.nf, w.M), share=False)
     want = ot.build(w.src, w.nf)
     groups_match_oracle(t.groups(), ot.groups(want), share=False)
+
+
+def permuted_workload(seed=7, **over):
+    """The mid workload with every flavour block of every term in a random
+    order (the input of the set-edge ablation)."""
+    w = W.workload("mid", **over)
+    rng = np.random.default_rng(seed)
+    for terms in (w.src, w.snk):
+        for u in range(len(terms)):
+            for o, k in ((0, w.nf[0]), (w.nf[0], w.nf[1])):
+                terms[u, o:o + k] = terms[u, o:o + k][rng.permutation(k)]
+    return w
+
+
+@pytest.mark.parametrize("prune", [False, True])
+@pytest.mark.parametrize("policy", ["R2", "R1"])
+def test_set_edge_tree_bit_exact(policy, prune):
+    w = permuted_workload(T=1, n_src=400)
+    t = mhc.Tree(mhc.Terms(w.src, w.nf, w.M), policy=policy, prune=prune, set_edges=True)
+    got = t.export()
+    want = ot.build(w.src, w.nf, policy=ot.R2 if policy == "R2" else ot.R1, prune_set=prune,
+                    edges="set")
+    assert got["n_dom"] == want["n_dom"]
+    for k in ("dom_order", "owner", "flav", "pos"):
+        np.testing.assert_array_equal(got[k], want[k], err_msg=k)
+    new, sign = t.children()
+    np.testing.assert_array_equal(new, want["new"])
+    np.testing.assert_array_equal(sign, want["sign"])
+    groups_match_oracle(t.groups(), ot.groups(want))
+    assert (sign == -1).any() and (sign == 1).any()
+
+
+def test_positional_tree_children_export():
+    w = W.workload("mid", T=1, n_src=300)
+    t = mhc.Tree(mhc.Terms(w.src, w.nf, w.M))
+    want = ot.build(w.src, w.nf)
+    new, sign = t.children()
+    np.testing.assert_array_equal(new, want["new"])
+    np.testing.assert_array_equal(sign, want["sign"])
