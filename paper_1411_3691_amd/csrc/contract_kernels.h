@@ -8,6 +8,22 @@
 namespace mhc {
 namespace kern {
 
+// Work of the multi-row group kernels for one method (update tree or plain
+// LU), all device memory.  A unit is a row set (a dominator, or a source
+// term for the plain LU) with a range of its groups and children; a tile is
+// a range of units and a range of sinks whose S rows one workgroup stages
+// in LDS at once.
+struct RowsTable {
+  int32_t n_tiles, max_rows;      // tiles; most rows any tile stages
+  const int4* tiles;              // [n_tiles] (u0, u1, s0, s1)
+  const int4* unit;               // [n_units] (row set, g0, g1, counts the row set's own term)
+  const int2* unit_c;             // [n_units] child range (update tree)
+  const int32_t* unit_row;        // [n_units + 1] a unit's staged rows: rows[unit_row[u] ..]
+  const int32_t* rows;            // S row index of every staged row: the row set's
+                                  // rows (flavour-major), then its children's new rows
+  const int32_t* child_lrow;      // [n_children] a child's new row within its unit
+};
+
 // Device tables of a plan (all pointers are device memory).
 struct PlanView {
   int32_t n_src, n_snk, n_snk_pad, M, F, sn, n_dom;
@@ -33,6 +49,8 @@ struct PlanView {
   const uint32_t* term_crow;      // [n_src]
   // sinks, position-major for coalesced loads; padded sinks repeat sink 0
   const uint32_t* snk_coloff;     // [sn][n_snk_pad] byte offset b*16
+  // multi-row group kernels (blocks up to 16); n_tiles 0 where not built
+  RowsTable rows_tree, rows_plain;
 };
 
 // Sink-side update tree (two-sided contraction).  Sink dominators are
@@ -109,6 +127,26 @@ hipError_t launch_contract(const ContractArgs& a, int n, bool tree, bool diag, i
 hipError_t launch_contract_wide(const ContractArgs& a, int nmax, bool tree, bool diag,
                                 double2* C, double* A, hipStream_t s, bool agg = false);
 int wide_sinks_per_wave(int nmax);
+
+// Multi-row group kernels (several rows of a matrix per lane, blocks up to
+// 16, sizes may differ per flavour): buckets 8, 12 and 16 (0 where no
+// bucket holds nmax).  Per workgroup: sinks per wave, waves and the bytes of
+// the pivot-row buffers; the rows a tile stages get the rest of the LDS.
+struct RowsGeometry {
+  int spw, waves;
+  size_t buf_bytes;
+};
+int rows_bucket(int nmax);
+RowsGeometry rows_geometry(int nmax, bool tree);
+// Enqueues the contraction by the plan's rows table of the method
+// (a.n_blk_t chunks per slice, each walking the tiles chunk, chunk +
+// n_blk_t, ...) and the final reduction; lds_rows = the table's max_rows
+// times the padded row bytes.
+hipError_t launch_contract_rows(const ContractArgs& a, int nmax, bool tree, bool with_a,
+                                bool agg, size_t lds_rows, double2* C, double* A, hipStream_t s);
+hipError_t launch_batch_rows(const BatchArgs& b, int nmax, bool tree, bool with_a, int grid,
+                             size_t lds_rows, hipStream_t s);
+int batch_rows_resident(int nmax, bool tree, bool with_a, size_t lds_rows);
 
 // Two-sided update trees (one matrix per lane, every block of size n <= 8):
 // work items are (source dominator, block of 64 sink dominators).

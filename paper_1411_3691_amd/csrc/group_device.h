@@ -32,14 +32,19 @@ __device__ __forceinline__ double dpp_move(double v) {
 constexpr int kDppRor8 = 0x128, kDppRor4 = 0x124, kDppRor2 = 0x122, kDppRor1 = 0x121;
 constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141;
 
-// Sum / max over the GROUP lanes of a group (8: three steps within each
-// half row; 16: rotations by 8, 4, 2, 1 within each row; 32: one more
-// exchange between the two rows).  Every lane combines the same values in
-// the same order up to commutation, so all lanes get the same bits.
+// Sum / max over the GROUP lanes of a group (4: two exchanges within each
+// quad; 8: three steps within each half row; 16: rotations by 8, 4, 2, 1
+// within each row; 32: one more exchange between the two rows).  Every lane
+// combines the same values in the same order up to commutation, so all
+// lanes get the same bits.
 template <int GROUP>
 __device__ __forceinline__ double group_sum(double v) {
-  static_assert(GROUP == 8 || GROUP == 16 || GROUP == 32, "groups are 8, 16 or 32 lanes");
-  if constexpr (GROUP == 8) {
+  static_assert(GROUP == 4 || GROUP == 8 || GROUP == 16 || GROUP == 32,
+                "groups are 4, 8, 16 or 32 lanes");
+  if constexpr (GROUP == 4) {
+    v += dpp_move<kDppXor1>(v);
+    v += dpp_move<kDppXor2>(v);
+  } else if constexpr (GROUP == 8) {
     v += dpp_move<kDppXor1>(v);
     v += dpp_move<kDppXor2>(v);
     v += dpp_move<kDppHalfMirror>(v);
@@ -55,8 +60,12 @@ __device__ __forceinline__ double group_sum(double v) {
 
 template <int GROUP>
 __device__ __forceinline__ double group_max(double v) {
-  static_assert(GROUP == 8 || GROUP == 16 || GROUP == 32, "groups are 8, 16 or 32 lanes");
-  if constexpr (GROUP == 8) {
+  static_assert(GROUP == 4 || GROUP == 8 || GROUP == 16 || GROUP == 32,
+                "groups are 4, 8, 16 or 32 lanes");
+  if constexpr (GROUP == 4) {
+    v = fmax(v, dpp_move<kDppXor1>(v));
+    v = fmax(v, dpp_move<kDppXor2>(v));
+  } else if constexpr (GROUP == 8) {
     v = fmax(v, dpp_move<kDppXor1>(v));
     v = fmax(v, dpp_move<kDppXor2>(v));
     v = fmax(v, dpp_move<kDppHalfMirror>(v));

@@ -43,6 +43,8 @@ struct mhc_plan {
   mhc::kern::SinkTreeView view_snk{};
   int32_t n_sdom = 0, n_sgroups = 0, n_schildren = 0;
   bool set_edges = false;              // the source tree has set edges
+  bool rows_built[2] = {false, false}; // multi-row tables: update tree, plain
+  std::vector<int4> rows_tiles[2];     // their tiles (host copy, for the batch's costs)
 };
 
 // Workgroup partial sums of mhc_contract_noalloc: a file-scope device array
@@ -59,6 +61,9 @@ constexpr int kSinkBlock = 64;
 // or faster than 1024, 2048 and 8192 for every lane-kernel method on the
 // mid workload (the plain LU 5 % faster than with 2048).
 constexpr int kTargetBlocks = 4096;
+// The LDS of one workgroup of the multi-row group kernels: 160 KiB less
+// 1 KiB for their static arrays.
+constexpr size_t kRowsLdsLimit = 159 * 1024;
 
 mhc_status hip_fail(hipError_t e, const char* where) {
   return fail(MHC_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
@@ -92,6 +97,118 @@ mhc_status noalloc_scratch(int dev, double** out) {
   }
   *out = g_scratch_ptr[dev];
   return MHC_OK;
+}
+
+// Units and tiles of the multi-row group kernels for one method (host
+// copy).  Tree: one unit per dominator, its rows (flavour-major) then the
+// distinct new rows of its children; a dominator whose rows exceed cap is
+// split by ranges of its children, each unit staging the dominator's rows
+// again (only the first counts the dominator's own term).  Plain: one unit
+// per source term.  Tiles take consecutive units while their rows fit cap
+// and their (unit, sink block) items stay within target; a unit with more
+// items than target is cut into tiles by ranges of sinks.
+struct RowsHost {
+  std::vector<int4> tiles, unit;
+  std::vector<int2> unit_c;
+  std::vector<int32_t> unit_row, rows, child_lrow;
+  int max_rows = 0;
+};
+
+bool build_rows(const mhc_terms& src, const mhc_tree* tree, int n_snk, int spw, int waves,
+                int cap, RowsHost& h) {
+  const int sn = src.sn;
+  if (cap < sn + 1 || spw < 1) return false;
+  h = RowsHost{};
+  h.unit_row.push_back(0);
+  auto add_unit = [&](int rs, int g0, int g1, bool primary, int c0, int c1,
+                      const std::vector<int32_t>& r) {
+    h.unit.push_back(make_int4(rs, g0, g1, primary ? 1 : 0));
+    h.unit_c.push_back(make_int2(c0, c1));
+    h.rows.insert(h.rows.end(), r.begin(), r.end());
+    h.unit_row.push_back((int32_t)h.rows.size());
+  };
+  if (!tree) {
+    for (int i = 0; i < src.n_terms; ++i) {
+      std::vector<int32_t> r(src.idx.begin() + (size_t)i * sn,
+                             src.idx.begin() + (size_t)(i + 1) * sn);
+      add_unit(i, 0, 0, true, 0, 0, r);
+    }
+  } else {
+    h.child_lrow.assign(tree->grp_child.size(), 0);
+    const int n_dom = (int)tree->dom_order.size();
+    for (int k = 0; k < n_dom; ++k) {
+      const int d = tree->dom_order[k];
+      const int gb = tree->dom_grp[k], ge = tree->dom_grp[k + 1];
+      const int cb = tree->grp_ptr[gb], ce = tree->grp_ptr[ge];
+      std::vector<int32_t> base(src.idx.begin() + (size_t)d * sn,
+                                src.idx.begin() + (size_t)(d + 1) * sn);
+      std::vector<int32_t> r = base;
+      int c0 = cb;
+      bool primary = true;
+      auto close = [&](int c1) {
+        // the groups whose children overlap [c0, c1)
+        int g0 = gb, g1 = gb;
+        if (c1 > c0) {
+          while (tree->grp_ptr[g0 + 1] <= c0) ++g0;
+          g1 = g0;
+          while (g1 < ge && tree->grp_ptr[g1] < c1) ++g1;
+        }
+        add_unit(k, g0, g1, primary, c0, c1, r);
+      };
+      for (int c = cb; c < ce; ++c) {
+        const int32_t row = tree->cnew[tree->grp_child[c]];
+        int at = -1;
+        for (size_t q = 0; q < r.size(); ++q)
+          if (r[q] == row) {
+            at = (int)q;
+            break;
+          }
+        if (at < 0) {
+          if ((int)r.size() + 1 > cap) {
+            close(c);
+            primary = false;
+            c0 = c;
+            r = base;
+          }
+          at = (int)r.size();
+          r.push_back(row);
+        }
+        h.child_lrow[c] = at;
+      }
+      close(ce);
+    }
+  }
+  // tiles
+  const int n_units = (int)h.unit.size();
+  const int n_sb = (n_snk + spw - 1) / spw;
+  const int target = std::max(waves * 32, 1);
+  int u = 0;
+  while (u < n_units) {
+    const int ur = h.unit_row[u + 1] - h.unit_row[u];
+    if (n_sb >= target || u + 1 == n_units) {
+      // this unit alone, cut by ranges of sinks
+      const int n_split = std::max(1, (n_sb + target - 1) / target);
+      const int per = (n_sb + n_split - 1) / n_split * spw;
+      for (int s0 = 0; s0 < n_snk; s0 += per)
+        h.tiles.push_back(make_int4(u, u + 1, s0, std::min(n_snk, s0 + per)));
+      h.max_rows = std::max(h.max_rows, ur);
+      ++u;
+      continue;
+    }
+    int u1 = u, rows = 0, items = 0;
+    while (u1 < n_units) {
+      const int r1 = h.unit_row[u1 + 1] - h.unit_row[u1];
+      if (u1 > u && (rows + r1 > cap || items + n_sb > target)) break;
+      rows += r1;
+      items += n_sb;
+      ++u1;
+    }
+    h.tiles.push_back(make_int4(u, u1, 0, n_snk));
+    h.max_rows = std::max(h.max_rows, rows);
+    u = u1;
+  }
+  if (n_snk == 0) h.tiles.clear();
+  return true;
 }
 
 }  // namespace
@@ -181,7 +298,32 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
           (uint32_t)snk->idx[(size_t)kk * sn + q] * 16u;
     }
 
+  // multi-row group kernels: the tables of both methods for the plan's
+  // bucket (none where the rows of one unit cannot fit the LDS)
+  RowsHost rows_h[2];
+  bool rows_ok[2] = {false, false};
+  if (mhc::kern::rows_bucket(nmax) > 0) {
+    for (int q = 0; q < 2; ++q) {
+      const mhc::kern::RowsGeometry geo = mhc::kern::rows_geometry(nmax, q == 0);
+      const size_t avail =
+          geo.buf_bytes < kRowsLdsLimit ? kRowsLdsLimit - geo.buf_bytes : 0;
+      const int cap = (int)(avail / row_bytes);
+      rows_ok[q] = build_rows(src, q == 0 ? tree : nullptr, snk->n_terms, geo.spw, geo.waves,
+                              cap, rows_h[q]);
+    }
+  }
+
   std::vector<char> img;
+  size_t o_rows[2][7] = {};
+  for (int q = 0; q < 2; ++q) {
+    if (!rows_ok[q]) continue;
+    o_rows[q][0] = append(img, rows_h[q].tiles);
+    o_rows[q][1] = append(img, rows_h[q].unit);
+    o_rows[q][2] = append(img, rows_h[q].unit_c);
+    o_rows[q][3] = append(img, rows_h[q].unit_row);
+    o_rows[q][4] = append(img, rows_h[q].rows);
+    o_rows[q][5] = append(img, rows_h[q].child_lrow);
+  }
   const size_t o_dom_term = append(img, dom_term);
   const size_t o_dom_rowoff = append(img, dom_rowoff);
   const size_t o_dom_grp = append(img, tree->dom_grp);
@@ -235,6 +377,23 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   v.term_owner = reinterpret_cast<const int32_t*>(base + o_term_owner);
   v.term_fr = reinterpret_cast<const int32_t*>(base + o_term_fr);
   v.term_crow = reinterpret_cast<const uint32_t*>(base + o_term_crow);
+  for (int q = 0; q < 2; ++q) {
+    mhc::kern::RowsTable& rt = q == 0 ? v.rows_tree : v.rows_plain;
+    rt = mhc::kern::RowsTable{};
+    if (!rows_ok[q]) continue;
+    rt.n_tiles = (int32_t)rows_h[q].tiles.size();
+    rt.max_rows = rows_h[q].max_rows;
+    rt.tiles = reinterpret_cast<const int4*>(base + o_rows[q][0]);
+    rt.unit = reinterpret_cast<const int4*>(base + o_rows[q][1]);
+    rt.unit_c = reinterpret_cast<const int2*>(base + o_rows[q][2]);
+    rt.unit_row = reinterpret_cast<const int32_t*>(base + o_rows[q][3]);
+    rt.rows = reinterpret_cast<const int32_t*>(base + o_rows[q][4]);
+    rt.child_lrow = reinterpret_cast<const int32_t*>(base + o_rows[q][5]);
+  }
+  pl->rows_built[0] = rows_ok[0];
+  pl->rows_built[1] = rows_ok[1];
+  pl->rows_tiles[0] = std::move(rows_h[0].tiles);
+  pl->rows_tiles[1] = std::move(rows_h[1].tiles);
   pl->fallback = reinterpret_cast<unsigned long long*>(base + o_fallback);
   pl->singular = pl->fallback + 1;
   *out = pl;
@@ -421,6 +580,12 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
   // one matrix per lane when every block has the same size n <= 8, else one
   // group of lanes per matrix
   const bool narrow = pl->uniform_n && pl->n <= 8;
+  // several rows of a matrix per lane (blocks up to 16), from the plan's
+  // tiles; the per-pair table and the other pivoting rules keep the
+  // one-row-per-lane kernels
+  const mhc::kern::RowsTable& rtab = tree ? pl->view.rows_tree : pl->view.rows_plain;
+  const bool rows = !narrow && !two && !dense_pairs && pivot == 1 &&
+                    pl->rows_built[tree ? 0 : 1] && rtab.n_tiles > 0;
   const int sinks_per_item = narrow ? kSinkBlock : mhc::kern::wide_sinks_per_wave(pl->n);
   const int waves_per_block = narrow ? 4 : 8;
   const int rowsets = (tree || two) ? pl->n_dom : pl->n_src;
@@ -430,7 +595,11 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
   if (n_items > 0x7fffffffLL)
     return fail(MHC_E_UNSUPPORTED, "mhc_contract: too many work items");
   int n_blk_t = (kTargetBlocks + T - 1) / T;
-  n_blk_t = (int)std::min<long long>(n_blk_t, (n_items + waves_per_block - 1) / waves_per_block);
+  if (rows)
+    n_blk_t = std::min(n_blk_t, rtab.n_tiles);
+  else
+    n_blk_t = (int)std::min<long long>(n_blk_t,
+                                       (n_items + waves_per_block - 1) / waves_per_block);
   n_blk_t = std::max(1, n_blk_t);
   const size_t need = (size_t)T * n_blk_t * 3;
   if (fixed) {
@@ -470,6 +639,11 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
   if (two)
     e = mhc::kern::launch_contract_two_sided(a, pl->n, static_cast<double2*>(C),
                                              reinterpret_cast<hipStream_t>(stream));
+  else if (rows)
+    e = mhc::kern::launch_contract_rows(
+        a, pl->n, tree, A != nullptr, agg,
+        (size_t)rtab.max_rows * mhc::kern::lds_row(pl->M) * 16, static_cast<double2*>(C), A,
+        reinterpret_cast<hipStream_t>(stream));
   else if (narrow)
     e = mhc::kern::launch_contract(a, pl->n, tree, diag, agg ? 3 : pivot,
                                    static_cast<double2*>(C), A,
@@ -633,10 +807,14 @@ struct mhc_batch {
 
 namespace {
 
+// Kernel families of a batch: one matrix per lane, one row per lane of a
+// group, several rows per lane of a group.
+enum BatchKind { kLane = 0, kWide = 1, kRows = 2 };
+
 struct Bucket {
-  bool narrow;
-  int n;          // block size (narrow) or bucket bound (group of lanes)
-  size_t lds;
+  int kind;
+  int n;          // block size (lane kernels) or bucket bound (groups of lanes)
+  size_t lds;     // slice of S (lane, wide) or most rows any tile stages (rows)
   std::vector<int4> tiles;
   std::vector<double> cost;
 };
@@ -676,6 +854,53 @@ mhc_status batch_build(mhc_batch* b) {
   for (int j = 0; j < nj; ++j) {
     mhc_plan* pl = b->plans[j];
     const bool narrow = use_lane_kernel(pl, b->sched.kernel);
+    const int q = tree ? 0 : 1;
+    const bool rows = !narrow && b->sched.kernel != MHC_SCHED_GROUP && pl->rows_built[q] &&
+                      !pl->rows_tiles[q].empty();
+    if (rows) {
+      // multi-row group kernels: one chunk per tile of the plan's table
+      const mhc::kern::RowsTable& rt = tree ? pl->view.rows_tree : pl->view.rows_plain;
+      const mhc::kern::RowsGeometry geo = mhc::kern::rows_geometry(pl->n, tree);
+      mhc::kern::ContractArgs& a = jobs[j];
+      a = mhc::kern::ContractArgs{};
+      a.plan = pl->view;
+      a.fallback = pl->fallback;
+      a.T = b->T[j];
+      a.n_blk_t = rt.n_tiles;
+      part_off[j] = part_total;
+      part_total += (size_t)a.T * rt.n_tiles * 3;
+      b->n_pairs += (int64_t)a.T * pl->n_src * pl->n_snk;
+      // predicted cost of one (unit, sink block) item: the eliminations,
+      // the solves, the dots
+      double item = 0.0;
+      for (int f = 0; f < pl->F; ++f) {
+        const double nf = pl->off[f + 1] - pl->off[f];
+        item += nf * nf * nf;
+      }
+      if (tree && pl->n_dom > 0)
+        item += (double)pl->n_groups / pl->n_dom * pl->n * pl->n +
+                (double)pl->n_children / pl->n_dom * pl->n;
+      item *= geo.spw;
+      const int key_n = mhc::kern::rows_bucket(pl->n);
+      Bucket* bk = nullptr;
+      for (auto& x : buckets)
+        if (x.kind == kRows && x.n == key_n) bk = &x;
+      if (!bk) {
+        buckets.push_back(Bucket{kRows, key_n, 0, {}, {}});
+        bk = &buckets.back();
+      }
+      bk->lds = std::max(bk->lds, (size_t)rt.max_rows * mhc::kern::lds_row(pl->M) * 16);
+      for (int t = 0; t < a.T; ++t) {
+        jt.push_back(make_int2(j, t));
+        for (int c = 0; c < rt.n_tiles; ++c) {
+          const int4 tl = pl->rows_tiles[q][c];
+          const double its = (double)(tl.y - tl.x) * ((tl.w - tl.z + geo.spw - 1) / geo.spw);
+          bk->tiles.push_back(make_int4(j, t, c, 0));
+          bk->cost.push_back(item * its);
+        }
+      }
+      continue;
+    }
     const int spi = narrow ? kSinkBlock : mhc::kern::wide_sinks_per_wave(pl->n);
     const int rowsets = tree ? pl->n_dom : pl->n_src;
     const int n_sblk = (pl->n_snk + spi - 1) / spi;
@@ -705,11 +930,12 @@ mhc_status batch_build(mhc_batch* b) {
               (double)pl->n_children / pl->n_dom * pl->n;
     item *= spi;
     const int key_n = narrow ? pl->n : mhc::kern::wide_bucket(pl->n);
+    const int kind = narrow ? kLane : kWide;
     Bucket* bk = nullptr;
     for (auto& x : buckets)
-      if (x.narrow == narrow && x.n == key_n) bk = &x;
+      if (x.kind == kind && x.n == key_n) bk = &x;
     if (!bk) {
-      buckets.push_back(Bucket{narrow, key_n, 0, {}, {}});
+      buckets.push_back(Bucket{kind, key_n, 0, {}, {}});
       bk = &buckets.back();
     }
     bk->lds = std::max(bk->lds, mhc::kern::lds_slice_bytes(pl->M));
@@ -771,14 +997,17 @@ mhc_status batch_build(mhc_batch* b) {
       // as many workgroups per compute unit as stay resident together (the
       // group kernels' registers and LDS decide; the lane kernels take two
       // where two copies of the slice fit in LDS)
-      per_cu = bk.narrow ? (bk.lds > 72 * 1024 ? 1 : 2)
-                         : std::min(8, mhc::kern::batch_wide_resident(bk.n, tree, b->with_a,
-                                                                      bk.lds));
+      per_cu = bk.kind == kLane ? (bk.lds > 72 * 1024 ? 1 : 2)
+               : bk.kind == kWide
+                   ? std::min(8, mhc::kern::batch_wide_resident(bk.n, tree, b->with_a, bk.lds))
+                   : std::min(8, mhc::kern::batch_rows_resident(bk.n, tree, b->with_a, bk.lds));
     }
     const int grid = std::max(1, std::min((int)ranges[i].second, n_cu * per_cu));
-    le = bk.narrow
+    le = bk.kind == kLane
              ? mhc::kern::launch_batch_lane(ba, bk.n, tree, b->with_a, grid, bk.lds, b->cap)
-             : mhc::kern::launch_batch_wide(ba, bk.n, tree, b->with_a, grid, bk.lds, b->cap);
+         : bk.kind == kWide
+             ? mhc::kern::launch_batch_wide(ba, bk.n, tree, b->with_a, grid, bk.lds, b->cap)
+             : mhc::kern::launch_batch_rows(ba, bk.n, tree, b->with_a, grid, bk.lds, b->cap);
   }
   if (le == hipSuccess) le = mhc::kern::launch_batch_reduce(b->jobs_dev, jt_dev, (int)jt.size(), b->cap);
   e = hipStreamEndCapture(b->cap, &b->graph);

@@ -1,0 +1,185 @@
+// Gauss-Jordan elimination with partial pivoting on matrices held by a
+// group of GROUP lanes with ROWS rows per lane (row i of the matrix lives in
+// lane i % GROUP, slot i / GROUP).  Several rows per lane let one broadcast
+// of the pivot row serve ROWS row updates and keep four lanes busy on a
+// 12 x 12 block instead of twelve of sixteen: per step the lanes issue
+// ROWS times more multiply-adds against the same chain of pivot search,
+// broadcast and reciprocal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "group_device.h"
+#include "lu_device.h"
+
+namespace mhc {
+namespace kern {
+
+// Complex entries of one group's pivot-row buffer (the row from column k
+// on, then the right-hand sides), rounded up to an odd count so that the
+// 16-byte reads of the groups of one wave fall in different LDS banks.
+template <int NMAX, int RMAX>
+constexpr int rows_buf_entries() {
+  return (NMAX + RMAX) | 1;
+}
+
+// Per-lane state of one elimination: ROWS rows of the matrix (columns <
+// NMAX) and of RB right-hand sides (storage; an elimination carries at most
+// its RMAX <= RB).
+template <int ROWS, int NMAX, int RMAX>
+struct RowsBlock {
+  double ar[ROWS][NMAX], ai[ROWS][NMAX];
+  double br[ROWS][RMAX], bi[ROWS][RMAX];
+};
+
+struct RowsResult {
+  double dre, dim;   // det G (the same in every lane of the group)
+  bool zero;         // some pivot was exactly zero
+};
+
+// Eliminates the group's n x n block (n <= NMAX, the same in every lane of
+// the wave) with nr <= RMAX right-hand sides.  Step k takes as pivot the
+// row not used yet with the largest |Re| + |Im| in column k, lowest row on
+// ties (the row index is packed into the low mantissa bits of the key, one
+// DPP max over the group); every other row subtracts l_i = a_ik / u times
+// the pivot row from its columns above k and from its right-hand sides.
+// Rows are relabelled, never moved: the pivot of column k stays in its row,
+// and later steps subtract only pivot rows whose column k is already zero,
+// so at the end row i reads u_i x[col_i] = b'_q[i].  Every pivot u is the
+// row's entry at its own column, and step k writes the pivot row from
+// column k on, so after the elimination entry c of the group's buffer holds
+// the pivot of step c: rows_pivot_inverse reads it back.
+// col[s] is set to the step at which slot s became a pivot row (-1 for
+// slots beyond n).  det G = the product of the pivots times the sign of the
+// pivot order (the pivots of GEPP).
+template <int GROUP, int ROWS, int NMAX, int RMAX, int RB>
+__device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB>& b, int nr,
+                                                        int n, int m, int (&col)[ROWS],
+                                                        double2* buf) {
+  static_assert(GROUP * ROWS >= NMAX, "the group must hold every row");
+  static_assert(GROUP * ROWS <= 32, "the row index is packed into 5 bits");
+  static_assert(RMAX <= RB, "right-hand sides beyond the block's storage");
+  RowsResult res{1.0, 0.0, false};
+  uint32_t used = 0u;        // bit s: slot s is a pivot row already
+  uint32_t parity = 0u;      // this lane's share of the pivot order's inversions
+#pragma unroll
+  for (int s = 0; s < ROWS; ++s) col[s] = -1;
+  static_for<0, NMAX>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if (k >= n) return;
+    // pivot: largest |Re| + |Im| of column k among the rows not used yet
+    double key = -1.0;
+#pragma unroll
+    for (int s = 0; s < ROWS; ++s) {
+      const int i = m + GROUP * s;
+      const double mag = fabs(b.ar[s][k]) + fabs(b.ai[s][k]);
+      const uint32_t lo = (__double2loint(mag) & ~31u) | (uint32_t)(31 - i);
+      const double ks = __hiloint2double(__double2hiint(mag), (int)lo);
+      const bool open = i < n && !((used >> s) & 1u);
+      key = open ? fmax(key, ks) : key;
+    }
+    key = group_max<GROUP>(key);
+    const int p = 31 - (int)(__double2loint(key) & 31u);   // pivot row, < n
+    const int lp = p % GROUP, sp = p / GROUP;
+    // sign: every row below p that is still open is one transposition of
+    // the pivot order
+#pragma unroll
+    for (int s = 0; s < ROWS; ++s) {
+      const int i = m + GROUP * s;
+      if (i < p && i < n && !((used >> s) & 1u)) parity ^= 1u;
+    }
+    if (m == lp) {
+      static_for<0, ROWS>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        if (s != sp) return;
+        static_for<k, NMAX>([&](auto cc) {
+          constexpr int c = decltype(cc)::value;
+          if (c < n) buf[c] = make_double2(b.ar[s][c], b.ai[s][c]);
+        });
+        static_for<0, RMAX>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          if (q < nr) buf[NMAX + q] = make_double2(b.br[s][q], b.bi[s][q]);
+        });
+      });
+    }
+    wave_lds_sync();
+    const double2 pv = buf[k];
+    const double pmag = fabs(pv.x) + fabs(pv.y);
+    res.zero = res.zero || (pmag == 0.0);
+    const double t = res.dre * pv.x - res.dim * pv.y;
+    res.dim = res.dre * pv.y + res.dim * pv.x;
+    res.dre = t;
+    double vr, vi;
+    cinv(pv.x, pv.y, pmag, vr, vi);   // 0 for a zero pivot
+    // multipliers (0 for the pivot row and for rows beyond n)
+    double lr[ROWS], li[ROWS];
+#pragma unroll
+    for (int s = 0; s < ROWS; ++s) {
+      const int i = m + GROUP * s;
+      const bool piv = i == p;
+      lr[s] = b.ar[s][k] * vr - b.ai[s][k] * vi;
+      li[s] = b.ar[s][k] * vi + b.ai[s][k] * vr;
+      if (piv || i >= n) {
+        lr[s] = 0.0;
+        li[s] = 0.0;
+      }
+      if (piv) {
+        used |= 1u << s;
+        col[s] = k;
+      }
+    }
+    static_for<k + 1, NMAX>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if (c >= n) return;
+      const double2 u = buf[c];
+#pragma unroll
+      for (int s = 0; s < ROWS; ++s) {
+        b.ar[s][c] = b.ar[s][c] - lr[s] * u.x + li[s] * u.y;
+        b.ai[s][c] = b.ai[s][c] - lr[s] * u.y - li[s] * u.x;
+      }
+    });
+    static_for<0, RMAX>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      if (q >= nr) return;
+      const double2 u = buf[NMAX + q];
+#pragma unroll
+      for (int s = 0; s < ROWS; ++s) {
+        b.br[s][q] = b.br[s][q] - lr[s] * u.x + li[s] * u.y;
+        b.bi[s][q] = b.bi[s][q] - lr[s] * u.y - li[s] * u.x;
+      }
+    });
+    wave_lds_sync();   // the row is read before the next step writes
+  });
+  // the group's inversions: the sum of the lanes' shares, mod 2
+  uint32_t par = parity;
+  if constexpr (GROUP >= 2)
+    par ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)par, kDppXor1, 0xf, 0xf, false);
+  if constexpr (GROUP >= 4)
+    par ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)par, kDppXor2, 0xf, 0xf, false);
+  if constexpr (GROUP >= 8)
+    par ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)par, kDppHalfMirror, 0xf, 0xf, false);
+  static_assert(GROUP <= 8, "parity reduction covers groups of up to 8 lanes");
+  if (par & 1u) {
+    res.dre = -res.dre;
+    res.dim = -res.dim;
+  }
+  return res;
+}
+
+// 1 / u for slot s's pivot, read back from the group's buffer (entry col of
+// the buffer holds the pivot of step col until the next elimination
+// writes it).  Slots without a pivot (beyond n) get 0.
+__device__ __forceinline__ void rows_pivot_inverse(const double2* buf, int col, double& vr,
+                                                   double& vi) {
+  vr = 0.0;
+  vi = 0.0;
+  if (col >= 0) {
+    const double2 u = buf[col];
+    cinv(u.x, u.y, fabs(u.x) + fabs(u.y), vr, vi);
+  }
+}
+
+}  // namespace kern
+}  // namespace mhc
