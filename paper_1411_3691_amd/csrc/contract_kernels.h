@@ -136,12 +136,21 @@ struct RowsGeometry {
   int spw, waves;
   size_t buf_bytes;
 };
+// Children whose (new row, weight) one tile stages in LDS, at most; the
+// plan splits tiles and units to keep within it.
+constexpr int kRowsChildCap = 256;
+// LDS of a workgroup besides the pivot-row buffers and the staged rows:
+// each wave's sink column offsets (spw sinks x sn positions) and the
+// tile's children table.
+__host__ __device__ constexpr size_t rows_meta_bytes(int waves, int spw, int sn) {
+  return ((size_t)waves * spw * sn * 4 + 15) / 16 * 16 + (size_t)kRowsChildCap * 16;
+}
 int rows_bucket(int nmax);
 RowsGeometry rows_geometry(int nmax, bool tree);
 // Enqueues the contraction by the plan's rows table of the method
 // (a.n_blk_t chunks per slice, each walking the tiles chunk, chunk +
-// n_blk_t, ...) and the final reduction; lds_rows = the table's max_rows
-// times the padded row bytes.
+// n_blk_t, ...) and the final reduction; lds_rows = rows_meta_bytes plus
+// the table's max_rows times the padded row bytes.
 hipError_t launch_contract_rows(const ContractArgs& a, int nmax, bool tree, bool with_a,
                                 bool agg, size_t lds_rows, double2* C, double* A, hipStream_t s);
 hipError_t launch_batch_rows(const BatchArgs& b, int nmax, bool tree, bool with_a, int grid,

@@ -156,6 +156,12 @@ bool build_rows(const mhc_terms& src, const mhc_tree* tree, int n_snk, int spw, 
         add_unit(k, g0, g1, primary, c0, c1, r);
       };
       for (int c = cb; c < ce; ++c) {
+        if (c - c0 >= mhc::kern::kRowsChildCap) {
+          close(c);
+          primary = false;
+          c0 = c;
+          r = base;
+        }
         const int32_t row = tree->cnew[tree->grp_child[c]];
         int at = -1;
         for (size_t q = 0; q < r.size(); ++q)
@@ -195,12 +201,16 @@ bool build_rows(const mhc_terms& src, const mhc_tree* tree, int n_snk, int spw, 
       ++u;
       continue;
     }
-    int u1 = u, rows = 0, items = 0;
+    int u1 = u, rows = 0, items = 0, kids = 0;
     while (u1 < n_units) {
       const int r1 = h.unit_row[u1 + 1] - h.unit_row[u1];
-      if (u1 > u && (rows + r1 > cap || items + n_sb > target)) break;
+      const int k1 = h.unit_c[u1].y - h.unit_c[u1].x;
+      if (u1 > u && (rows + r1 > cap || items + n_sb > target ||
+                     kids + k1 > mhc::kern::kRowsChildCap))
+        break;
       rows += r1;
       items += n_sb;
+      kids += k1;
       ++u1;
     }
     h.tiles.push_back(make_int4(u, u1, 0, n_snk));
@@ -209,6 +219,15 @@ bool build_rows(const mhc_terms& src, const mhc_tree* tree, int n_snk, int spw, 
   }
   if (n_snk == 0) h.tiles.clear();
   return true;
+}
+
+// LDS of a multi-row launch beyond the pivot-row buffers: the wave and
+// tile tables and the most rows any tile of the method's table stages.
+size_t rows_lds_bytes(const mhc_plan* pl, bool tree) {
+  const mhc::kern::RowsGeometry geo = mhc::kern::rows_geometry(pl->n, tree);
+  const mhc::kern::RowsTable& rt = tree ? pl->view.rows_tree : pl->view.rows_plain;
+  return mhc::kern::rows_meta_bytes(geo.waves, geo.spw, pl->sn) +
+         (size_t)rt.max_rows * mhc::kern::lds_row(pl->M) * 16;
 }
 
 }  // namespace
@@ -305,8 +324,8 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   if (mhc::kern::rows_bucket(nmax) > 0) {
     for (int q = 0; q < 2; ++q) {
       const mhc::kern::RowsGeometry geo = mhc::kern::rows_geometry(nmax, q == 0);
-      const size_t avail =
-          geo.buf_bytes < kRowsLdsLimit ? kRowsLdsLimit - geo.buf_bytes : 0;
+      const size_t fixed = geo.buf_bytes + mhc::kern::rows_meta_bytes(geo.waves, geo.spw, sn);
+      const size_t avail = fixed < kRowsLdsLimit ? kRowsLdsLimit - fixed : 0;
       const int cap = (int)(avail / row_bytes);
       rows_ok[q] = build_rows(src, q == 0 ? tree : nullptr, snk->n_terms, geo.spw, geo.waves,
                               cap, rows_h[q]);
@@ -642,7 +661,7 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
   else if (rows)
     e = mhc::kern::launch_contract_rows(
         a, pl->n, tree, A != nullptr, agg,
-        (size_t)rtab.max_rows * mhc::kern::lds_row(pl->M) * 16, static_cast<double2*>(C), A,
+        rows_lds_bytes(pl, tree), static_cast<double2*>(C), A,
         reinterpret_cast<hipStream_t>(stream));
   else if (narrow)
     e = mhc::kern::launch_contract(a, pl->n, tree, diag, agg ? 3 : pivot,
@@ -889,7 +908,7 @@ mhc_status batch_build(mhc_batch* b) {
         buckets.push_back(Bucket{kRows, key_n, 0, {}, {}});
         bk = &buckets.back();
       }
-      bk->lds = std::max(bk->lds, (size_t)rt.max_rows * mhc::kern::lds_row(pl->M) * 16);
+      bk->lds = std::max(bk->lds, rows_lds_bytes(pl, tree));
       for (int t = 0; t < a.T; ++t) {
         jt.push_back(make_int2(j, t));
         for (int c = 0; c < rt.n_tiles; ++c) {

@@ -34,13 +34,27 @@ struct RowsBlock {
   double br[ROWS][RMAX], bi[ROWS][RMAX];
 };
 
+// Largest of a 32-bit value over the GROUP lanes of a group (4 or 8).
+template <int GROUP>
+__device__ __forceinline__ uint32_t group_max_u32(uint32_t v) {
+  static_assert(GROUP == 4 || GROUP == 8, "groups of 4 or 8 lanes");
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppXor1, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppXor2, 0xf, 0xf, false));
+  if constexpr (GROUP == 8)
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppHalfMirror, 0xf, 0xf,
+                                                       false));
+  return v;
+}
+
 struct RowsResult {
   double dre, dim;   // det G (the same in every lane of the group)
   bool zero;         // some pivot was exactly zero
 };
 
 // Eliminates the group's n x n block (n <= NMAX, the same in every lane of
-// the wave) with nr <= RMAX right-hand sides.  Step k takes as pivot the
+// the wave; columns n .. NMAX-1 must hold zeros, rows n .. are ignored)
+// with RMAX right-hand sides (unused ones may hold anything finite: no
+// per-entry guards, so the steps compile without branches).  Step k takes as pivot the
 // row not used yet with the largest |Re| + |Im| in column k, lowest row on
 // ties (the row index is packed into the low mantissa bits of the key, one
 // DPP max over the group); every other row subtracts l_i = a_ik / u times
@@ -54,34 +68,41 @@ struct RowsResult {
 // col[s] is set to the step at which slot s became a pivot row (-1 for
 // slots beyond n).  det G = the product of the pivots times the sign of the
 // pivot order (the pivots of GEPP).
-template <int GROUP, int ROWS, int NMAX, int RMAX, int RB>
-__device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB>& b, int nr,
-                                                        int n, int m, int (&col)[ROWS],
-                                                        double2* buf) {
+// KEEP: every row also keeps its multiplier of step k in its column k and
+// pivots records the pivot row of every step (4 bits each), so that
+// rows_replay can apply the same row operations to more right-hand sides.
+template <int GROUP, int ROWS, int NMAX, int RMAX, int RB, bool KEEP = false>
+__device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB>& b, int n,
+                                                        int m, int (&col)[ROWS],
+                                                        double2* buf, uint64_t& pivots) {
   static_assert(GROUP * ROWS >= NMAX, "the group must hold every row");
-  static_assert(GROUP * ROWS <= 32, "the row index is packed into 5 bits");
+  static_assert(GROUP * ROWS <= 16, "the row index is packed into 5 bits above 15");
   static_assert(RMAX <= RB, "right-hand sides beyond the block's storage");
   RowsResult res{1.0, 0.0, false};
+  pivots = 0ull;
   uint32_t used = 0u;        // bit s: slot s is a pivot row already
   uint32_t parity = 0u;      // this lane's share of the pivot order's inversions
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) col[s] = -1;
-  static_for<0, NMAX>([&](auto kc) {
+  static_for<0, NMAX>([&](auto kc) __attribute__((always_inline)) {
     constexpr int k = decltype(kc)::value;
     if (k >= n) return;
-    // pivot: largest |Re| + |Im| of column k among the rows not used yet
-    double key = -1.0;
+    // pivot: largest |Re| + |Im| of column k among the rows not used yet.
+    // The key is the magnitude's high word (non-negative doubles order as
+    // their bits) with the row in its 5 low bits, so rows within 2^-15 of
+    // the largest count as ties, taken lowest row first; closed rows get 0
+    // (open keys are >= 16 since rows are < 16).
+    uint32_t key = 0u;
 #pragma unroll
     for (int s = 0; s < ROWS; ++s) {
       const int i = m + GROUP * s;
       const double mag = fabs(b.ar[s][k]) + fabs(b.ai[s][k]);
-      const uint32_t lo = (__double2loint(mag) & ~31u) | (uint32_t)(31 - i);
-      const double ks = __hiloint2double(__double2hiint(mag), (int)lo);
+      const uint32_t ks = ((uint32_t)__double2hiint(mag) & ~31u) | (uint32_t)(31 - i);
       const bool open = i < n && !((used >> s) & 1u);
-      key = open ? fmax(key, ks) : key;
+      key = max(key, open ? ks : 0u);
     }
-    key = group_max<GROUP>(key);
-    const int p = 31 - (int)(__double2loint(key) & 31u);   // pivot row, < n
+    key = group_max_u32<GROUP>(key);
+    const int p = 31 - (int)(key & 31u);   // pivot row, < n
     const int lp = p % GROUP, sp = p / GROUP;
     // sign: every row below p that is still open is one transposition of
     // the pivot order
@@ -91,16 +112,24 @@ __device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB
       if (i < p && i < n && !((used >> s) & 1u)) parity ^= 1u;
     }
     if (m == lp) {
-      static_for<0, ROWS>([&](auto sc) {
+      static_for<0, ROWS>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         if (s != sp) return;
-        static_for<k, NMAX>([&](auto cc) {
+        // Each value passes an empty statement in its own branch: otherwise
+        // the compiler merges the slots' branches into one store of a value
+        // read through a computed slot index, which keeps the rows in
+        // scratch memory instead of registers.
+        static_for<k, NMAX>([&](auto cc) __attribute__((always_inline)) {
           constexpr int c = decltype(cc)::value;
-          if (c < n) buf[c] = make_double2(b.ar[s][c], b.ai[s][c]);
+          const double xr = b.ar[s][c], xi = b.ai[s][c];
+          asm volatile("" ::"v"(xr), "v"(xi));
+          buf[c] = make_double2(xr, xi);
         });
-        static_for<0, RMAX>([&](auto qc) {
+        static_for<0, RMAX>([&](auto qc) __attribute__((always_inline)) {
           constexpr int q = decltype(qc)::value;
-          if (q < nr) buf[NMAX + q] = make_double2(b.br[s][q], b.bi[s][q]);
+          const double xr = b.br[s][q], xi = b.bi[s][q];
+          asm volatile("" ::"v"(xr), "v"(xi));
+          buf[NMAX + q] = make_double2(xr, xi);
         });
       });
     }
@@ -113,26 +142,27 @@ __device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB
     res.dre = t;
     double vr, vi;
     cinv(pv.x, pv.y, pmag, vr, vi);   // 0 for a zero pivot
-    // multipliers (0 for the pivot row and for rows beyond n)
+    // multipliers (0 for the pivot row; rows beyond n follow along with
+    // finite values and are never read)
     double lr[ROWS], li[ROWS];
 #pragma unroll
     for (int s = 0; s < ROWS; ++s) {
       const int i = m + GROUP * s;
       const bool piv = i == p;
-      lr[s] = b.ar[s][k] * vr - b.ai[s][k] * vi;
-      li[s] = b.ar[s][k] * vi + b.ai[s][k] * vr;
-      if (piv || i >= n) {
-        lr[s] = 0.0;
-        li[s] = 0.0;
-      }
-      if (piv) {
-        used |= 1u << s;
-        col[s] = k;
+      const double wr = piv ? 0.0 : vr, wi = piv ? 0.0 : vi;
+      lr[s] = b.ar[s][k] * wr - b.ai[s][k] * wi;
+      li[s] = b.ar[s][k] * wi + b.ai[s][k] * wr;
+      used |= piv ? 1u << s : 0u;
+      col[s] = piv ? k : col[s];
+      if constexpr (KEEP) {
+        // column k is not read again: it keeps the multiplier for replays
+        b.ar[s][k] = lr[s];
+        b.ai[s][k] = li[s];
       }
     }
-    static_for<k + 1, NMAX>([&](auto cc) {
+    if constexpr (KEEP) pivots |= (uint64_t)p << (4 * k);
+    static_for<k + 1, NMAX>([&](auto cc) __attribute__((always_inline)) {
       constexpr int c = decltype(cc)::value;
-      if (c >= n) return;
       const double2 u = buf[c];
 #pragma unroll
       for (int s = 0; s < ROWS; ++s) {
@@ -140,9 +170,8 @@ __device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB
         b.ai[s][c] = b.ai[s][c] - lr[s] * u.y - li[s] * u.x;
       }
     });
-    static_for<0, RMAX>([&](auto qc) {
+    static_for<0, RMAX>([&](auto qc) __attribute__((always_inline)) {
       constexpr int q = decltype(qc)::value;
-      if (q >= nr) return;
       const double2 u = buf[NMAX + q];
 #pragma unroll
       for (int s = 0; s < ROWS; ++s) {
@@ -166,6 +195,48 @@ __device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB
     res.dim = -res.dim;
   }
   return res;
+}
+
+// Applies the row operations of rows_gauss_jordan<..., KEEP> (multipliers
+// in the matrix columns, pivot rows in pivots) to RB right-hand sides at
+// once: step k subtracts each row's multiplier times the pivot row's
+// entries, so that on return the system reads u_i x[col_i] = b'_q[i], as if
+// the columns had been carried through the elimination.  One pass serves
+// all RB columns: its chain of broadcasts costs a fraction of another
+// elimination.  Uses the right-hand-side part of the group's buffer only;
+// the pivots in its first entries stay for rows_pivot_inverse.
+template <int GROUP, int ROWS, int NMAX, int RB>
+__device__ __forceinline__ void rows_replay(RowsBlock<ROWS, NMAX, RB>& b, int n, int m,
+                                            uint64_t pivots, double2* buf) {
+  static_for<0, NMAX>([&](auto kc) __attribute__((always_inline)) {
+    constexpr int k = decltype(kc)::value;
+    if (k >= n) return;
+    const int p = (int)((pivots >> (4 * k)) & 15ull);
+    const int lp = p % GROUP, sp = p / GROUP;
+    if (m == lp) {
+      static_for<0, ROWS>([&](auto sc) __attribute__((always_inline)) {
+        constexpr int s = decltype(sc)::value;
+        if (s != sp) return;
+        static_for<0, RB>([&](auto qc) __attribute__((always_inline)) {
+          constexpr int q = decltype(qc)::value;
+          const double xr = b.br[s][q], xi = b.bi[s][q];
+          asm volatile("" ::"v"(xr), "v"(xi));
+          buf[NMAX + q] = make_double2(xr, xi);
+        });
+      });
+    }
+    wave_lds_sync();
+    static_for<0, RB>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+      const double2 u = buf[NMAX + q];
+#pragma unroll
+      for (int s = 0; s < ROWS; ++s) {
+        b.br[s][q] = b.br[s][q] - b.ar[s][k] * u.x + b.ai[s][k] * u.y;
+        b.bi[s][q] = b.bi[s][q] - b.ar[s][k] * u.y - b.ai[s][k] * u.x;
+      }
+    });
+    wave_lds_sync();
+  });
 }
 
 // 1 / u for slot s's pivot, read back from the group's buffer (entry col of

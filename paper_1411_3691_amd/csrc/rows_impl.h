@@ -69,12 +69,37 @@ constexpr size_t rows_buf_bytes() {
   return (size_t)(C::WB / C::GROUP) * rows_buf_entries<NMAX, rows_rmax<NMAX, TREE>()>() * 16;
 }
 
+// A child of the current tile as staged in LDS.
+struct ChildInfo {
+  uint32_t crow;   // byte offset of its new row among the staged rows
+  uint32_t pad;
+  double wc;       // its weight times the sign of its row permutation
+};
+
+// A read of plan tables at a wave-uniform index through the constant
+// address space, so that it becomes a scalar load (the kernels write
+// global memory, and through a generic pointer the compiler keeps such
+// reads on the vector path, one memory latency per read).
+template <class T>
+__device__ __forceinline__ T cload(const T* ptr, long i) {
+  static_assert(sizeof(T) % 4 == 0, "read by 32-bit words");
+  const __attribute__((address_space(4))) uint32_t* q =
+      (const __attribute__((address_space(4))) uint32_t*)(ptr + i);
+  T v;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(T) / 4); ++w) d[w] = q[w];
+  return v;
+}
+
 // One chunk of slice t: tiles chunk, chunk + n_blk_t, ... of the method's
 // table.  MODE bit 0: accumulate A(t); bit 4: weighted-row aggregation of
 // each group's children (one dot per group, no per-child value).
-template <int NMAX, bool TREE, int MODE>
-__device__ __forceinline__ void rows_chunk(const ContractArgs& a, int t, int chunk,
-                                           double2* smem) {
+// ARGS: the job's ContractArgs, a kernel argument or an entry of the
+// batch's job table read through the constant address space (its fields
+// then come by scalar loads where they are used).
+template <int NMAX, bool TREE, int MODE, class ARGS>
+__device__ __forceinline__ void rows_chunk(ARGS& a, int t, int chunk, double2* smem) {
   using Cfg = RowsCfg<NMAX>;
   constexpr int GROUP = Cfg::GROUP, ROWS = Cfg::ROWS, WB = Cfg::WB;
   constexpr int RMAX = rows_rmax<NMAX, TREE>();
@@ -85,32 +110,75 @@ __device__ __forceinline__ void rows_chunk(const ContractArgs& a, int t, int chu
   constexpr bool WITH_A = (MODE & 1) != 0;
   constexpr bool AGG = (MODE & 16) != 0;
   static_assert(!(AGG && WITH_A), "aggregation forms no per-child values");
-  const PlanView& p = a.plan;
-  const RowsTable& rt = TREE ? p.rows_tree : p.rows_plain;
+  const auto& p = a.plan;
+  const auto& rt = TREE ? p.rows_tree : p.rows_plain;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uniform(threadIdx.x / kWave);
   const int m = lane % GROUP;      // the group's lane holding rows m, m + GROUP, ...
   const int gsel = lane / GROUP;   // which sink of the wave's block
+  // LDS: pivot-row buffers | each wave's sink column offsets | the tile's
+  // children (new row, weight) | the staged rows of S_t
+  const int sn = p.sn;
   double2* buf = smem + (threadIdx.x / GROUP) * E;
-  double2* rows = smem + (WB / GROUP) * E;
+  char* meta = reinterpret_cast<char*>(smem) + (size_t)(WB / GROUP) * E * 16;
+  uint32_t* wco = reinterpret_cast<uint32_t*>(meta) + wave * SPW * sn;
+  ChildInfo* chi = reinterpret_cast<ChildInfo*>(
+      meta + ((size_t)kWaves * SPW * sn * 4 + 15) / 16 * 16);
+  double2* rows = reinterpret_cast<double2*>(meta + rows_meta_bytes(kWaves, SPW, sn));
   const char* lds = reinterpret_cast<const char*>(rows);
   const int M = p.M;
   const uint32_t stride = (uint32_t)lds_row(M) * 16u;
   const double2* St = a.S + (size_t)t * M * M;
   const int F = p.F;
+  const int n_tiles = rt.n_tiles;
 
   double acc_re = 0.0, acc_im = 0.0, acc_a = 0.0;
   uint32_t n_fallback = 0;
 
-  for (int ti = chunk; ti < rt.n_tiles; ti += a.n_blk_t) {
-    const int u0 = uniform(rt.tiles[ti].x), u1 = uniform(rt.tiles[ti].y);
-    const int s0 = uniform(rt.tiles[ti].z), s1 = uniform(rt.tiles[ti].w);
-    const int r0 = uniform(rt.unit_row[u0]);
-    const int nrows = uniform(rt.unit_row[u1]) - r0;
+  for (int ti = chunk; ti < n_tiles; ti += a.n_blk_t) {
+    const int4 tl = cload(rt.tiles, ti);
+    const int u0 = tl.x, u1 = tl.y, s0 = tl.z, s1 = tl.w;
+    const int r0 = cload(rt.unit_row, u0);
+    const int nrows = cload(rt.unit_row, u1) - r0;
     __syncthreads();   // the previous tile is done with the rows
-    for (int e = threadIdx.x; e < nrows * M; e += WB) {
-      const int r = e / M, c = e - r * M;
-      rows[r * lds_row(M) + c] = St[(size_t)rt.rows[r0 + r] * M + c];
+    {
+      // four entries in flight per thread
+      constexpr int U = 4;
+      const int total = nrows * M;
+      for (int e0 = threadIdx.x; e0 < total; e0 += U * WB) {
+        double2 v[U];
+        int dst[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          const int e = e0 + q * WB;
+          dst[q] = -1;
+          if (e < total) {
+            const int r = e / M, c = e - r * M;
+            v[q] = St[(size_t)rt.rows[r0 + r] * M + c];
+            dst[q] = r * lds_row(M) + c;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+          if (dst[q] >= 0) rows[dst[q]] = v[q];
+      }
+    }
+    // the tile's children: byte offset of the new row in LDS and weight
+    // times the sign of the row permutation
+    int tc0 = 0;
+    if (TREE) {
+      tc0 = cload(rt.unit_c, u0).x;
+      for (int u = u0 + wave; u < u1; u += kWaves) {
+        const int2 uc = cload(rt.unit_c, u);
+        const uint32_t ub = (uint32_t)(cload(rt.unit_row, u) - r0);
+        for (int c = uc.x + lane; c < uc.y; c += kWave) {
+          ChildInfo ci;
+          ci.crow = (ub + (uint32_t)rt.child_lrow[c]) * stride;
+          ci.pad = 0u;
+          ci.wc = a.w_src[p.child_term[c]] * p.child_wsgn[c];
+          chi[c - tc0] = ci;
+        }
+      }
     }
     __syncthreads();
     const int n_sb = (s1 - s0 + SPW - 1) / SPW;
@@ -123,40 +191,61 @@ __device__ __forceinline__ void rows_chunk(const ContractArgs& a, int t, int chu
       const int k = s0 + sb * SPW + gsel;
       const bool valid = k < s1;
       const int kk = valid ? k : s0;   // lanes past the range compute sink s0, masked
-      const int4 ui = rt.unit[u];
-      const int rs = uniform(ui.x);
-      const bool primary = uniform(ui.w) != 0;
-      const int term = TREE ? uniform(p.dom_term[rs]) : rs;
-      const uint32_t ubase = (uint32_t)(uniform(rt.unit_row[u]) - r0) * stride;
-      const int g_begin = TREE ? uniform(ui.y) : 0;
-      const int g_end = TREE ? uniform(ui.z) : 0;
-      const int c_lo = TREE ? uniform(rt.unit_c[u].x) : 0;
-      const int c_hi = TREE ? uniform(rt.unit_c[u].y) : 0;
+      const int4 ui = cload(rt.unit, u);
+      const int rs = ui.x;
+      const bool primary = ui.w != 0;
+      const int term = TREE ? cload(p.dom_term, rs) : rs;
+      const uint32_t ubase = (uint32_t)(cload(rt.unit_row, u) - r0) * stride;
+      const int g_begin = TREE ? ui.y : 0;
+      const int g_end = TREE ? ui.z : 0;
+      int c_lo = 0, c_hi = 0;
+      if (TREE) {
+        const int2 uc = cload(rt.unit_c, u);
+        c_lo = uc.x;
+        c_hi = uc.y;
+      }
+      // this wave's sink column offsets: wco[q * SPW + g] for position q
+      // of sink s0 + sb * SPW + g (padded sinks repeat sink s0)
+      for (int e = lane; e < SPW * sn; e += kWave) {
+        const int q = e / SPW, gl = e - q * SPW;
+        const int k2 = s0 + sb * SPW + gl;
+        wco[e] = p.snk_coloff[(size_t)q * p.n_snk_pad + (k2 < s1 ? k2 : s0)];
+      }
+      wave_lds_sync();
 
       // The group's block of flavour f: the row set's rows, row rrep
       // replaced by the LDS row at crow (a child's), columns of sink kk.
-      auto load_block = [&](int f, int rrep, uint32_t crow, RowsBlock<ROWS, NMAX, RB>& blk) {
+      // Rows past n read the set's first row (never pivots, multiplier 0);
+      // columns past n are zero and never read.
+      auto load_block = [&](int f, int rrep, uint32_t crow, RowsBlock<ROWS, NMAX, RB>& blk)
+                            __attribute__((always_inline)) {
         const int o = p.off[f];
         const int n = p.off[f + 1] - o;
-        const uint32_t* cof = p.snk_coloff + (size_t)o * p.n_snk_pad + kk;
-        uint32_t co[NMAX];
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c) co[c] = c < n ? cof[(size_t)c * p.n_snk_pad] : 0u;
+        const uint32_t* cof = wco + (size_t)o * SPW + gsel;
+        uint32_t ra[ROWS];
 #pragma unroll
         for (int s = 0; s < ROWS; ++s) {
           const int i = m + GROUP * s;
-          const uint32_t ra = (i == rrep) ? crow : ubase + (uint32_t)(o + i) * stride;
+          ra[s] = (i == rrep) ? crow : ubase + (uint32_t)(o + (i < n ? i : 0)) * stride;
+        }
+        static_for<0, NMAX>([&](auto cc) __attribute__((always_inline)) {
+          constexpr int c = decltype(cc)::value;
+          if (c < n) {
+            const uint32_t co = cof[c * SPW];
 #pragma unroll
-          for (int c = 0; c < NMAX; ++c) {
-            blk.ar[s][c] = 0.0;
-            blk.ai[s][c] = 0.0;
-            if (c < n && i < n) {
-              const double2 v = *reinterpret_cast<const double2*>(lds + ra + co[c]);
+            for (int s = 0; s < ROWS; ++s) {
+              const double2 v = *reinterpret_cast<const double2*>(lds + ra[s] + co);
               blk.ar[s][c] = v.x;
               blk.ai[s][c] = v.y;
             }
+          } else {
+#pragma unroll
+            for (int s = 0; s < ROWS; ++s) {
+              blk.ar[s][c] = 0.0;
+              blk.ai[s][c] = 0.0;
+            }
           }
-        }
+        });
       };
 
       // P: product of the blocks' dets (the same in every lane of the
@@ -172,7 +261,7 @@ __device__ __forceinline__ void rows_chunk(const ContractArgs& a, int t, int chu
         const int n = p.off[f + 1] - o;
         int g_f_end = g;
         if (TREE) {
-          while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
+          while (g_f_end < g_end && (cload(p.grp_fr, g_f_end) >> 8) == f) ++g_f_end;
         }
         const int R = g_f_end - g;
         const int npass = (TREE && R > RB) ? (R + RB - 1) / RB : 1;
@@ -181,117 +270,133 @@ __device__ __forceinline__ void rows_chunk(const ContractArgs& a, int t, int chu
         // over flavours is Q <- D Q + (D P) sum_c w_c ratio_c, P <- D P: the
         // first elimination applies D at once, so that only P and Q stay
         // live across the eliminations.
-        for (int pass = 0; pass < npass; ++pass) {
-          const int g0 = pass * RB;
-          const int nr = TREE ? min(R - g0, RB) : 0;
-          RowsBlock<ROWS, NMAX, RB> blk;
-          load_block(f, -1, 0u, blk);
+        RowsBlock<ROWS, NMAX, RB> blk;
+        load_block(f, -1, 0u, blk);
+        auto set_units = [&](int g0) __attribute__((always_inline)) {
+          const int nr = min(R - g0, RB);
 #pragma unroll
           for (int q = 0; q < RB; ++q) {
-            const int r = q < nr ? uniform(p.grp_fr[g + g0 + q] & 0xff) : -1;
+            const int r = q < nr ? (cload(p.grp_fr, g + g0 + q) & 0xff) : -1;
 #pragma unroll
             for (int s = 0; s < ROWS; ++s) {
               blk.br[s][q] = (m + GROUP * s == r) ? 1.0 : 0.0;
               blk.bi[s][q] = 0.0;
             }
           }
-          int col[ROWS];
-          const RowsResult res =
-              rows_gauss_jordan<GROUP, ROWS, NMAX, RMAX, RB>(blk, nr, n, m, col, buf);
-          if (pass == 0) {
-            const double qr = Qre * res.dre - Qim * res.dim;
-            Qim = Qre * res.dim + Qim * res.dre;
-            Qre = qr;
-            const double pr = Pre * res.dre - Pim * res.dim;
-            Pim = Pre * res.dim + Pim * res.dre;
-            Pre = pr;
-          }
-          // no inverse: the item goes the direct route below (a plain LU
-          // needs none, its det is 0)
-          if (res.zero) bad = true;
-          if (!TREE || bad) continue;
-          // x_q[col_i] = b'_q[i] / u_i for this lane's rows; the children's
-          // rows are read at those columns
-          const uint32_t* cof = p.snk_coloff + (size_t)o * p.n_snk_pad + kk;
+        };
+        if (TREE) set_units(0);
+        int col[ROWS];
+        uint64_t pivots;
+        const RowsResult res =
+            rows_gauss_jordan<GROUP, ROWS, NMAX, RMAX, RB, TREE>(blk, n, m, col, buf, pivots);
+        {
+          const double qr = Qre * res.dre - Qim * res.dim;
+          Qim = Qre * res.dim + Qim * res.dre;
+          Qre = qr;
+          const double pr = Pre * res.dre - Pim * res.dim;
+          Pim = Pre * res.dim + Pim * res.dre;
+          Pre = pr;
+        }
+        // no inverse: the item goes the direct route below (a plain LU
+        // needs none, its det is 0)
+        if (res.zero) bad = true;
+        if (TREE && !bad) {
+          // x_q[col_i] = b'_q[i] / u_i for this lane's rows (0 for rows
+          // past n); the children's rows are read at those columns
+          const uint32_t* cof = wco + (size_t)o * SPW + gsel;
           double vr[ROWS], vi[ROWS];
           uint32_t mycol[ROWS];
 #pragma unroll
           for (int s = 0; s < ROWS; ++s) {
             rows_pivot_inverse(buf, col[s], vr[s], vi[s]);
-            mycol[s] = col[s] >= 0 ? cof[(size_t)col[s] * p.n_snk_pad] : 0u;
+            mycol[s] = cof[(col[s] >= 0 ? col[s] : 0) * SPW];
           }
-          double sre = 0.0, sim = 0.0;   // sum_c w_c ratio_c (or this lane's share)
-          static_for<0, RB>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            if (q >= nr) return;
-            double xr[ROWS], xi[ROWS];
-#pragma unroll
-            for (int s = 0; s < ROWS; ++s) {
-              xr[s] = blk.br[s][q] * vr[s] - blk.bi[s][q] * vi[s];
-              xi[s] = blk.br[s][q] * vi[s] + blk.bi[s][q] * vr[s];
+          // groups of this block RB at a time: the first RB rode through
+          // the elimination, the others replay its row operations
+          for (int pass = 0; pass < npass; ++pass) {
+            const int g0 = pass * RB;
+            const int nr = min(R - g0, RB);
+            if (pass > 0) {
+              set_units(g0);
+              rows_replay<GROUP, ROWS, NMAX, RB>(blk, n, m, pivots, buf);
             }
-            const int gg = g + g0 + q;
-            const int cb = max(uniform(p.grp_ptr[gg]), c_lo);
-            const int ce = min(uniform(p.grp_ptr[gg + 1]), c_hi);
-            if constexpr (AGG) {
-              // multilinearity in row r: the children's weighted rows are
-              // summed first (at this lane's columns), then dotted once
-              double hr[ROWS], hi[ROWS];
-#pragma unroll
+            double sre = 0.0, sim = 0.0;   // sum_c w_c ratio_c (or this lane's share)
+            static_for<0, RB>([&](auto qc) __attribute__((always_inline)) {
+              constexpr int q = decltype(qc)::value;
+              if (q >= nr) return;
+              double xr[ROWS], xi[ROWS];
+  #pragma unroll
               for (int s = 0; s < ROWS; ++s) {
-                hr[s] = 0.0;
-                hi[s] = 0.0;
+                xr[s] = blk.br[s][q] * vr[s] - blk.bi[s][q] * vi[s];
+                xi[s] = blk.br[s][q] * vi[s] + blk.bi[s][q] * vr[s];
               }
-              for (int c = cb; c < ce; ++c) {
-                const uint32_t cr = ubase + (uint32_t)uniform(rt.child_lrow[c]) * stride;
-                const double wc = a.w_src[uniform(p.child_term[c])] * p.child_wsgn[c];
-#pragma unroll
+              const int gg = g + g0 + q;
+              const int cb = max(cload(p.grp_ptr, gg), c_lo);
+              const int ce = min(cload(p.grp_ptr, gg + 1), c_hi);
+              if constexpr (AGG) {
+                // multilinearity in row r: the children's weighted rows are
+                // summed first (at this lane's columns), then dotted once
+                double hr[ROWS], hi[ROWS];
+  #pragma unroll
                 for (int s = 0; s < ROWS; ++s) {
-                  if (col[s] >= 0) {
-                    const double2 sv = *reinterpret_cast<const double2*>(lds + cr + mycol[s]);
-                    hr[s] += wc * sv.x;
-                    hi[s] += wc * sv.y;
+                  hr[s] = 0.0;
+                  hi[s] = 0.0;
+                }
+                for (int c = cb; c < ce; ++c) {
+                  const ChildInfo ci = chi[c - tc0];
+                  const uint32_t cr = ci.crow;
+                  const double wc = ci.wc;
+                  double2 sv[ROWS];
+  #pragma unroll
+                  for (int s = 0; s < ROWS; ++s)
+                    sv[s] = *reinterpret_cast<const double2*>(lds + cr + mycol[s]);
+  #pragma unroll
+                  for (int s = 0; s < ROWS; ++s) {
+                    hr[s] += wc * sv[s].x;
+                    hi[s] += wc * sv[s].y;
                   }
                 }
+  #pragma unroll
+                for (int s = 0; s < ROWS; ++s) {
+                  sre += hr[s] * xr[s] - hi[s] * xi[s];
+                  sim += hr[s] * xi[s] + hi[s] * xr[s];
+                }
+                return;
               }
-#pragma unroll
-              for (int s = 0; s < ROWS; ++s) {
-                sre += hr[s] * xr[s] - hi[s] * xi[s];
-                sim += hr[s] * xi[s] + hi[s] * xr[s];
-              }
-              return;
-            }
-            for (int c = cb; c < ce; ++c) {
-              const uint32_t cr = ubase + (uint32_t)uniform(rt.child_lrow[c]) * stride;
-              const double wc = a.w_src[uniform(p.child_term[c])] * p.child_wsgn[c];
-              double pr_ = 0.0, pi_ = 0.0;
-#pragma unroll
-              for (int s = 0; s < ROWS; ++s) {
-                if (col[s] >= 0) {
-                  const double2 sv = *reinterpret_cast<const double2*>(lds + cr + mycol[s]);
-                  pr_ += sv.x * xr[s] - sv.y * xi[s];
-                  pi_ += sv.x * xi[s] + sv.y * xr[s];
+              for (int c = cb; c < ce; ++c) {
+                const ChildInfo ci = chi[c - tc0];
+                const uint32_t cr = ci.crow;
+                const double wc = ci.wc;
+                double2 sv[ROWS];
+  #pragma unroll
+                for (int s = 0; s < ROWS; ++s)
+                  sv[s] = *reinterpret_cast<const double2*>(lds + cr + mycol[s]);
+                double pr_ = 0.0, pi_ = 0.0;
+  #pragma unroll
+                for (int s = 0; s < ROWS; ++s) {
+                  pr_ += sv[s].x * xr[s] - sv[s].y * xi[s];
+                  pi_ += sv[s].x * xi[s] + sv[s].y * xr[s];
+                }
+                if constexpr (WITH_A) {
+                  const double rr = group_sum<GROUP>(pr_);
+                  const double ri = group_sum<GROUP>(pi_);
+                  sre += wc * rr;
+                  sim += wc * ri;
+                  sabs_reg += fabs(wc) * cabs_scaled(rr, ri);
+                } else {
+                  sre += wc * pr_;
+                  sim += wc * pi_;
                 }
               }
-              if constexpr (WITH_A) {
-                const double rr = group_sum<GROUP>(pr_);
-                const double ri = group_sum<GROUP>(pi_);
-                sre += wc * rr;
-                sim += wc * ri;
-                sabs_reg += fabs(wc) * cabs_scaled(rr, ri);
-              } else {
-                sre += wc * pr_;
-                sim += wc * pi_;
-              }
-            }
-          });
-          Qre += Pre * sre - Pim * sim;
-          Qim += Pre * sim + Pim * sre;
+            });
+            Qre += Pre * sre - Pim * sim;
+            Qim += Pre * sim + Pim * sre;
+          }
         }
         g = g_f_end;
       }
 
-      const double wi = a.w_src[term];
+      const double wi = cload(a.w_src, term);
       const double wd = primary ? wi : 0.0;
       const double wk = valid ? a.w_snk[kk] : 0.0;
       if (TREE) bad = bad && (g_end > g_begin);   // no children: nothing to redo
@@ -316,25 +421,26 @@ __device__ __forceinline__ void rows_chunk(const ContractArgs& a, int t, int chu
         double Ure = wd * Pre, Uim = wd * Pim;
         double uab = fabs(wd) * cabs_scaled(Pre, Pim);
         int gq = g_begin;
-        const int cb = max(uniform(p.grp_ptr[g_begin]), c_lo);
-        const int ce = min(uniform(p.grp_ptr[g_end]), c_hi);
+        const int cb = max(cload(p.grp_ptr, g_begin), c_lo);
+        const int ce = min(cload(p.grp_ptr, g_end), c_hi);
         for (int c = cb; c < ce; ++c) {
-          while (uniform(p.grp_ptr[gq + 1]) <= c) ++gq;
-          const int fc = uniform(p.grp_fr[gq] >> 8);
-          const int rc = uniform(p.grp_fr[gq] & 0xff);
-          const uint32_t crow = ubase + (uint32_t)uniform(rt.child_lrow[c]) * stride;
-          double dr = p.child_wsgn[c], di = 0.0;
+          while (cload(p.grp_ptr, gq + 1) <= c) ++gq;
+          const int fc = cload(p.grp_fr, gq) >> 8;
+          const int rc = cload(p.grp_fr, gq) & 0xff;
+          const uint32_t crow = ubase + (uint32_t)cload(rt.child_lrow, c) * stride;
+          double dr = cload(p.child_wsgn, c), di = 0.0;
           for (int f = 0; f < F; ++f) {
             RowsBlock<ROWS, NMAX, RB> blk;
             load_block(f, f == fc ? rc : -1, crow, blk);
             int col[ROWS];
+            uint64_t pivots;
             const RowsResult res = rows_gauss_jordan<GROUP, ROWS, NMAX, 0, RB>(
-                blk, 0, p.off[f + 1] - p.off[f], m, col, buf);
+                blk, p.off[f + 1] - p.off[f], m, col, buf, pivots);
             const double tr = dr * res.dre - di * res.dim;
             di = dr * res.dim + di * res.dre;
             dr = tr;
           }
-          const double wc = a.w_src[uniform(p.child_term[c])];
+          const double wc = cload(a.w_src, cload(p.child_term, c));
           Ure += wc * dr;
           Uim += wc * di;
           if (WITH_A) uab += fabs(wc) * cabs_scaled(dr, di);
@@ -382,8 +488,10 @@ template <int NMAX, bool TREE, int MODE>
 __global__ __launch_bounds__(RowsCfg<NMAX>::WB) void batch_rows_kernel(BatchArgs b) {
   extern __shared__ double2 smem[];
   for (int i = blockIdx.x; i < b.n_tiles; i += gridDim.x) {
-    const int4 tl = b.tiles[i];
-    rows_chunk<NMAX, TREE, MODE>(b.jobs[tl.x], tl.y, tl.z, smem);
+    const int4 tl = cload(b.tiles, i);
+    const __attribute__((address_space(4))) ContractArgs& a =
+        ((const __attribute__((address_space(4))) ContractArgs*)b.jobs)[tl.x];
+    rows_chunk<NMAX, TREE, MODE>(a, tl.y, tl.z, smem);
   }
 }
 
