@@ -332,10 +332,9 @@ mhc_status mhc_plan_attach_sink_tree(mhc_plan* plan, const mhc_tree* snk_tree, v
  * Schedule (every field 0 = chosen by the library):
  *   kernel          MHC_SCHED_AUTO: one matrix per lane where every flavour
  *                   block of a job has the same size n <= 8, else a group of
- *                   lanes per matrix (several rows per lane for blocks up to
- *                   16, one row per lane above); MHC_SCHED_LANE forces one
- *                   matrix per lane (refused for other jobs),
- *                   MHC_SCHED_GROUP one row per lane of a group;
+ *                   lanes per matrix (several rows per lane);
+ *                   MHC_SCHED_LANE forces one matrix per lane (refused for
+ *                   other jobs), MHC_SCHED_GROUP one row per lane of a group;
  *   blocks_per_cu   persistent workgroups per compute unit, in [0, 8];
  *   items_per_tile  work items per tile, >= 0 (one row per lane only; the
  *                   several-rows kernels take the plan's tiles).

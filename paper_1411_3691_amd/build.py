@@ -29,7 +29,8 @@ COMMON = [
 
 SOURCES = ["mhc_host.cpp", "mhc_plan.hip", "contract_kernels.hip", "wide_kernels.hip",
            "wide_b8.hip", "wide_b12.hip", "wide_b16.hip", "wide_b18.hip", "wide_b24.hip",
-           "rows_kernels.hip", "rows_b8.hip", "rows_b12.hip", "rows_b16.hip",
+           "rows_kernels.hip", "rows_b8.hip", "rows_b12.hip", "rows_b16.hip", "rows_b18.hip",
+           "rows_b24.hip",
            "adjoint_kernels.hip", "tree2_kernels.hip", "probe_kernels.hip", "pair_kernels.hip"]
 
 

@@ -49,7 +49,7 @@ struct PlanView {
   const uint32_t* term_crow;      // [n_src]
   // sinks, position-major for coalesced loads; padded sinks repeat sink 0
   const uint32_t* snk_coloff;     // [sn][n_snk_pad] byte offset b*16
-  // multi-row group kernels (blocks up to 16); n_tiles 0 where not built
+  // multi-row group kernels (blocks up to 24); n_tiles 0 where not built
   RowsTable rows_tree, rows_plain;
 };
 
@@ -129,8 +129,8 @@ hipError_t launch_contract_wide(const ContractArgs& a, int nmax, bool tree, bool
 int wide_sinks_per_wave(int nmax);
 
 // Multi-row group kernels (several rows of a matrix per lane, blocks up to
-// 16, sizes may differ per flavour): buckets 8, 12 and 16 (0 where no
-// bucket holds nmax).  Per workgroup: sinks per wave, waves and the bytes of
+// 24, sizes may differ per flavour): buckets 8, 12, 16, 18 and 24 (0 where
+// no bucket holds nmax).  Per workgroup: sinks per wave, waves and the bytes of
 // the pivot-row buffers; the rows a tile stages get the rest of the LDS.
 struct RowsGeometry {
   int spw, waves;

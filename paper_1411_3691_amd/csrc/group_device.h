@@ -28,9 +28,9 @@ __device__ __forceinline__ double dpp_move(double v) {
 
 // DPP controls: row_ror:R rotates a row of 16 by R; quad_perm [1,0,3,2] and
 // [2,3,0,1] swap neighbours and pairs within each quad; row_half_mirror
-// reverses each half row of 8.
+// reverses each half row of 8, row_mirror each row of 16.
 constexpr int kDppRor8 = 0x128, kDppRor4 = 0x124, kDppRor2 = 0x122, kDppRor1 = 0x121;
-constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141;
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppRowMirror = 0x140;
 
 // Sum / max over the GROUP lanes of a group (4: two exchanges within each
 // quad; 8: three steps within each half row; 16: rotations by 8, 4, 2, 1

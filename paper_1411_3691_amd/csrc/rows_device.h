@@ -37,14 +37,24 @@ struct RowsBlock {
 // Largest of a 32-bit value over the GROUP lanes of a group (4 or 8).
 template <int GROUP>
 __device__ __forceinline__ uint32_t group_max_u32(uint32_t v) {
-  static_assert(GROUP == 4 || GROUP == 8, "groups of 4 or 8 lanes");
+  static_assert(GROUP == 4 || GROUP == 8 || GROUP == 16, "groups of 4, 8 or 16 lanes");
   v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppXor1, 0xf, 0xf, false));
   v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppXor2, 0xf, 0xf, false));
-  if constexpr (GROUP == 8)
+  if constexpr (GROUP >= 8)
     v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppHalfMirror, 0xf, 0xf,
+                                                       false));
+  if constexpr (GROUP >= 16)
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowMirror, 0xf, 0xf,
                                                        false));
   return v;
 }
+
+// Pivot rows of the steps of one elimination, 5 bits each.
+template <int NMAX>
+struct PivotRows {
+  uint32_t w[(NMAX + 5) / 6];
+  __device__ __forceinline__ int get(int k) const { return (w[k / 6] >> (5 * (k % 6))) & 31; }
+};
 
 struct RowsResult {
   double dre, dim;   // det G (the same in every lane of the group)
@@ -69,17 +79,19 @@ struct RowsResult {
 // slots beyond n).  det G = the product of the pivots times the sign of the
 // pivot order (the pivots of GEPP).
 // KEEP: every row also keeps its multiplier of step k in its column k and
-// pivots records the pivot row of every step (4 bits each), so that
+// pivots records the pivot row of every step, so that
 // rows_replay can apply the same row operations to more right-hand sides.
 template <int GROUP, int ROWS, int NMAX, int RMAX, int RB, bool KEEP = false>
 __device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB>& b, int n,
                                                         int m, int (&col)[ROWS],
-                                                        double2* buf, uint64_t& pivots) {
+                                                        double2* buf, PivotRows<NMAX>& pivots) {
   static_assert(GROUP * ROWS >= NMAX, "the group must hold every row");
-  static_assert(GROUP * ROWS <= 16, "the row index is packed into 5 bits above 15");
+  static_assert(GROUP * ROWS <= 32 && NMAX <= 24,
+                "the row index is packed into 5 bits; open rows < 24 keep keys above 7");
   static_assert(RMAX <= RB, "right-hand sides beyond the block's storage");
   RowsResult res{1.0, 0.0, false};
-  pivots = 0ull;
+#pragma unroll
+  for (int w = 0; w < (NMAX + 5) / 6; ++w) pivots.w[w] = 0u;
   uint32_t used = 0u;        // bit s: slot s is a pivot row already
   uint32_t parity = 0u;      // this lane's share of the pivot order's inversions
 #pragma unroll
@@ -91,7 +103,7 @@ __device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB
     // The key is the magnitude's high word (non-negative doubles order as
     // their bits) with the row in its 5 low bits, so rows within 2^-15 of
     // the largest count as ties, taken lowest row first; closed rows get 0
-    // (open keys are >= 16 since rows are < 16).
+    // (open rows are < 24, so their keys are >= 8).
     uint32_t key = 0u;
 #pragma unroll
     for (int s = 0; s < ROWS; ++s) {
@@ -160,7 +172,7 @@ __device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB
         b.ai[s][k] = li[s];
       }
     }
-    if constexpr (KEEP) pivots |= (uint64_t)p << (4 * k);
+    if constexpr (KEEP) pivots.w[k / 6] |= (uint32_t)p << (5 * (k % 6));
     static_for<k + 1, NMAX>([&](auto cc) __attribute__((always_inline)) {
       constexpr int c = decltype(cc)::value;
       const double2 u = buf[c];
@@ -189,7 +201,9 @@ __device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB
     par ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)par, kDppXor2, 0xf, 0xf, false);
   if constexpr (GROUP >= 8)
     par ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)par, kDppHalfMirror, 0xf, 0xf, false);
-  static_assert(GROUP <= 8, "parity reduction covers groups of up to 8 lanes");
+  if constexpr (GROUP >= 16)
+    par ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)par, kDppRowMirror, 0xf, 0xf, false);
+  static_assert(GROUP <= 16, "parity reduction covers groups of up to 16 lanes");
   if (par & 1u) {
     res.dre = -res.dre;
     res.dim = -res.dim;
@@ -207,11 +221,11 @@ __device__ __forceinline__ RowsResult rows_gauss_jordan(RowsBlock<ROWS, NMAX, RB
 // the pivots in its first entries stay for rows_pivot_inverse.
 template <int GROUP, int ROWS, int NMAX, int RB>
 __device__ __forceinline__ void rows_replay(RowsBlock<ROWS, NMAX, RB>& b, int n, int m,
-                                            uint64_t pivots, double2* buf) {
+                                            const PivotRows<NMAX>& pivots, double2* buf) {
   static_for<0, NMAX>([&](auto kc) __attribute__((always_inline)) {
     constexpr int k = decltype(kc)::value;
     if (k >= n) return;
-    const int p = (int)((pivots >> (4 * k)) & 15ull);
+    const int p = pivots.get(k);
     const int lp = p % GROUP, sp = p / GROUP;
     if (m == lp) {
       static_for<0, ROWS>([&](auto sc) __attribute__((always_inline)) {

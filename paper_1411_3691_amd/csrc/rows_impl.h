@@ -1,4 +1,4 @@
-// Contraction kernels for flavour blocks up to 16 with several rows of a
+// Contraction kernels for flavour blocks up to 24 with several rows of a
 // matrix per lane (gfx950): the templates, instantiated per block-size
 // bucket by rows_b*.hip.
 //
@@ -46,15 +46,23 @@ template <int NMAX>
 struct RowsCfg;
 template <>
 struct RowsCfg<8> {
-  static constexpr int GROUP = 4, ROWS = 2, RMAX = 6, WB = 768;
+  static constexpr int GROUP = 4, ROWS = 2, RMAX = 4, WB = 768;
 };
 template <>
 struct RowsCfg<12> {
-  static constexpr int GROUP = 4, ROWS = 3, RMAX = 4, WB = 512;
+  static constexpr int GROUP = 4, ROWS = 3, RMAX = 2, WB = 512;
 };
 template <>
 struct RowsCfg<16> {
-  static constexpr int GROUP = 8, ROWS = 2, RMAX = 4, WB = 512;
+  static constexpr int GROUP = 8, ROWS = 2, RMAX = 2, WB = 512;
+};
+template <>
+struct RowsCfg<18> {
+  static constexpr int GROUP = 16, ROWS = 2, RMAX = 2, WB = 512;
+};
+template <>
+struct RowsCfg<24> {
+  static constexpr int GROUP = 16, ROWS = 2, RMAX = 1, WB = 512;
 };
 
 template <int NMAX, bool TREE>
@@ -286,7 +294,7 @@ __device__ __forceinline__ void rows_chunk(ARGS& a, int t, int chunk, double2* s
         };
         if (TREE) set_units(0);
         int col[ROWS];
-        uint64_t pivots;
+        PivotRows<NMAX> pivots;
         const RowsResult res =
             rows_gauss_jordan<GROUP, ROWS, NMAX, RMAX, RB, TREE>(blk, n, m, col, buf, pivots);
         {
@@ -433,7 +441,7 @@ __device__ __forceinline__ void rows_chunk(ARGS& a, int t, int chunk, double2* s
             RowsBlock<ROWS, NMAX, RB> blk;
             load_block(f, f == fc ? rc : -1, crow, blk);
             int col[ROWS];
-            uint64_t pivots;
+            PivotRows<NMAX> pivots;
             const RowsResult res = rows_gauss_jordan<GROUP, ROWS, NMAX, 0, RB>(
                 blk, p.off[f + 1] - p.off[f], m, col, buf, pivots);
             const double tr = dr * res.dre - di * res.dim;

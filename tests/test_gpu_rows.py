@@ -1,5 +1,5 @@
 """GPU parity of the multi-row group kernels (several rows of a matrix per
-lane, blocks up to 16, rows of S staged per tile): the correlator of the
+lane, blocks up to 24, rows of S staged per tile): the correlator of the
 fast path, the scale A and the weighted-row aggregation against the CPU
 oracle, on uneven and M = 96 shapes, dominators split over several tiles,
 singular dominator blocks and repeated runs."""
@@ -43,6 +43,10 @@ def check_all_methods(w, plan, S, ws, wk, methods=("plain", "tree", "tree_agg"))
     ((10, 11), 30, 140, 33),        # bucket 12, uneven
     ((16,), 30, 90, 21),            # bucket 16, 8 lanes x 2 rows exactly
     ((9, 16), 40, 80, 26),          # bucket 16, uneven
+    ((17, 5), 40, 60, 20),          # bucket 18, 16 lanes x 2 rows
+    ((18, 2), 30, 60, 9),           # bucket 18, the batch's largest block
+    ((24,), 30, 24, 7),             # bucket 24, the largest supported block
+    ((20, 13), 48, 50, 12),         # bucket 24, uneven
 ])
 def test_rows_kernels_match_oracle(nf, M, n_src, n_snk):
     w = W.workload("mid", T=2, M=M, nf=nf, n_src=n_src, n_snk=n_snk, branching=4, depth=3)
@@ -51,7 +55,7 @@ def test_rows_kernels_match_oracle(nf, M, n_src, n_snk):
     check_all_methods(w, plan, S, ws, wk)
 
 
-@pytest.mark.parametrize("nf", [(5, 7), (12, 12), (16, 10)])
+@pytest.mark.parametrize("nf", [(5, 7), (12, 12), (16, 10), (18, 9), (22,)])
 def test_rows_kernels_m96(nf):
     # 96 quark indices: a full slice would not fit beside the pivot-row
     # buffers; the tiles stage only their units' rows
