@@ -37,21 +37,21 @@ SETTLE_S = 0.3              # untimed work before the first timed method
 # HBM bytes per launch of the update-tree kernel on the mid workload, from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script
 # (--copy-probe), each scaled by the same counter's reading for a 256 MiB
-# device copy (fetch x 1.99972, write x 1.0).  Valid only for the kernel
+# device copy (fetch x 1.99976, write x 1.0).  Valid only for the kernel
 # and launch-configuration sources they were measured on (SHA-256 below);
 # null otherwise.
 TRAFFIC = {
     "workload": "mid",
-    "bytes": 7781.1 * 1.99972 * 1024 + 5312.0 * 1024,
+    "bytes": 7893.1 * 1.99976 * 1024 + 5312.0 * 1024,
     "sources": {
         "paper_1411_3691_amd/csrc/contract_kernels.hip":
-            "880b92fb3b12869b225efccf1476066c78d5fa010b4d19ba824912c832c8182a",
+            "9fbec0acae9e4cc410113541fe0e7dbcf87dd8592a82e48ce87713d28948a851",
         "paper_1411_3691_amd/csrc/lu_device.h":
-            "3b5b2c5914bf701a7f937f97ce9876223e749d29c081dd58c93b9736918c6756",
+            "21f197e72234e5ee4a485bded6b317888a70e29d7c2be9e200832ed2fd87a45a",
         "paper_1411_3691_amd/csrc/mhc_plan.hip":
-            "f0a269bec0c0f4c30f0b4e1f8437fc74d3e6f66bc502b5f29526244d23289f98",
+            "272ff9d3bf57d6babd532f2dbe6ec7016c6cb633d950f8c587b09127aa8fa5b5",
         "paper_1411_3691_amd/csrc/contract_kernels.h":
-            "bc0486545e82593f3f41324d36fe1545d163913d26540dbc00a6858f71a8445b",
+            "d53228083f7853eb0096367886288e4d9c6c4d122cb0e6e1f141e8a77b923e6d",
     },
 }
 
