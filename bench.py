@@ -179,6 +179,27 @@ def fma_probe(dev, iters: int = 4096, n_blocks: int = 4096, reps: int = 10) -> f
     return flop / (e0.elapsed_time(e1) * 1e-3) / 1e12
 
 
+def mfma_probe(dev, with_valu: bool, iters: int = 2048, n_blocks: int = 4096,
+               reps: int = 5) -> float:
+    """Measured FP64 matrix-core rate (TFLOP/s) of this GPU: 4 independent
+    v_mfma_f64_16x16x4_f64 chains per wave (with_valu: plus the 16 vector
+    FMA chains per thread, counted in the rate), timed as fma_probe."""
+    import torch
+    from paper_1411_3691_amd import mhc
+    out = torch.empty(n_blocks * mhc.PROBE_BLOCK, dtype=torch.float64, device=dev)
+    for _ in range(2):
+        mhc.probe_mfma64(out, iters, with_valu)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    flop = 0
+    for _ in range(reps):
+        flop += mhc.probe_mfma64(out, iters, with_valu)
+    e1.record()
+    torch.cuda.synchronize()
+    return flop / (e0.elapsed_time(e1) * 1e-3) / 1e12
+
+
 def plain_flops(T, n_src, n_snk, nf) -> float:
     return float(T) * n_src * n_snk * (sum(f_lu(n) for n in nf) + 11)
 
@@ -410,6 +431,8 @@ def bench_workload(w, args, steps: int, warmup: int, plain_steps: int, plain_war
             torch.cuda.synchronize()
 
     fma = fma_probe(dev) if probe else None
+    mfma = ({"tflops": mfma_probe(dev, False), "tflops_with_vector_fma": mfma_probe(dev, True)}
+            if probe else None)
 
     cur = {"plan": plan}
 
@@ -454,6 +477,43 @@ def bench_workload(w, args, steps: int, warmup: int, plain_steps: int, plain_war
                                        "kernel_ms": float(np.mean(ev_a)),
                                        "value": w.n_pairs / (wall_a / steps),
                                        "n_groups": tree_ns.stats()["n_groups"]}
+        # weighted-row aggregation (an extension: one dot per group of
+        # siblings; no per-pair values, so it is not the headline)
+        wall_a, ev_a, C_agg = timed("tree_agg")
+        abl["tree_aggregation"] = {
+            "ms_per_step": wall_a * 1e3 / steps, "kernel_ms": float(np.mean(ev_a)),
+            "value": w.n_pairs / (wall_a / steps),
+            "max_rel_diff_vs_tree": float(np.max(np.abs(C_agg - C_tree)) /
+                                          max(1e-300, float(np.max(np.abs(C_tree)))))}
+        # set-based edges: the same terms with every flavour block listed in
+        # a random order; positional edges then see few neighbours, set
+        # edges (with the permutation sign) see the forest again
+        rng = np.random.default_rng(20141113)
+        offs = np.concatenate([[0], np.cumsum(w.nf)])
+        perm_idx = {}
+        for side, terms in (("src", w.src), ("snk", w.snk)):
+            t2 = terms.copy()
+            for u in range(len(t2)):
+                for f in range(len(w.nf)):
+                    o, k = offs[f], w.nf[f]
+                    t2[u, o:o + k] = t2[u, o:o + k][rng.permutation(k)]
+            perm_idx[side] = t2
+        src_p = mhc.Terms(perm_idx["src"], w.nf, w.M)
+        snk_p = mhc.Terms(perm_idx["snk"], w.nf, w.M)
+        set_res = {}
+        for lbl, se in (("positional_edges", False), ("set_edges", True)):
+            tr_p = mhc.Tree(src_p, set_edges=se)
+            cur["plan"] = mhc.Plan(tr_p, snk_p)
+            wall_a, ev_a, C_p = timed("tree")
+            set_res[lbl] = {"ms_per_step": wall_a * 1e3 / steps,
+                            "kernel_ms": float(np.mean(ev_a)),
+                            "value": w.n_pairs / (wall_a / steps),
+                            "n_dom": tr_p.stats()["n_dom"], "C": C_p}
+        cur["plan"] = plan
+        c_pos, c_set = set_res["positional_edges"].pop("C"), set_res["set_edges"].pop("C")
+        set_res["max_rel_diff"] = float(np.max(np.abs(c_set - c_pos)) /
+                                        max(1e-300, float(np.max(np.abs(c_pos)))))
+        abl["permuted_terms"] = set_res
         log(f"{name}: ablations done")
     if extras and name in ("mid", "large"):
         # reverse-delete dominating set: fewer dominators, same sum
@@ -564,6 +624,8 @@ def bench_workload(w, args, steps: int, warmup: int, plain_steps: int, plain_war
     if fma is not None:
         out["fp64_fma_probe"] = {"tflops": fma, "frac_of_peak": fma / FP64_PEAK_TFLOPS,
                                  "tree_frac_of_probe": rf["achieved"] / fma}
+    if mfma is not None:
+        out["fp64_mfma_probe"] = mfma
     if extras:
         out["two_sided"] = two
         out["ablations"] = abl

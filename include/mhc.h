@@ -386,6 +386,18 @@ void mhc_batch_destroy(mhc_batch* batch);
  * [1, 2^24]), MHC_E_DEVICE (launch failure). */
 mhc_status mhc_probe_fma64(double* out, int32_t n_blocks, int32_t iters, void* stream);
 
+/* Device probe (not an operation of the paper): the FP64 matrix-core rate,
+ * to compare with mhc_probe_fma64.  Every thread runs `iters` rounds of 4
+ * independent v_mfma_f64_16x16x4_f64 accumulations (per wave and round
+ * 4 x 2048 flop); with_valu != 0 adds the 16 vector FMA chains of
+ * mhc_probe_fma64 to every round (32 flop per thread), to measure whether
+ * matrix and vector FP64 work add up.  out[thread] receives the sum of the
+ * thread's accumulator entries and chain values.  Launch, arguments and
+ * errors as for mhc_probe_fma64; flop per launch = n_blocks * 4 waves *
+ * iters * 8192 (+ n_blocks * 256 * iters * 32 with with_valu). */
+mhc_status mhc_probe_mfma64(double* out, int32_t n_blocks, int32_t iters, int32_t with_valu,
+                            void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,7 @@ SIGNATURES = {
     "mhc_batch_info": (_I32, [_P, _PI32, _PI32, _PI64]),
     "mhc_batch_destroy": (None, [_P]),
     "mhc_probe_fma64": (_I32, [_PD, _I32, _I32, _P]),
+    "mhc_probe_mfma64": (_I32, [_PD, _I32, _I32, _I32, _P]),
 }
 
 

@@ -260,6 +260,23 @@ def probe_fma64(out: torch.Tensor, iters: int) -> int:
     return out.numel() * iters * PROBE_FLOP_PER_ROUND
 
 
+def probe_mfma64(out: torch.Tensor, iters: int, with_valu: bool = False) -> int:
+    """Enqueue the FP64 matrix-core probe (mhc_probe_mfma64) on torch's
+    current stream; out as for probe_fma64.  Returns the flop count of the
+    launch (matrix and, with with_valu, vector)."""
+    if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 GPU tensor")
+    if out.numel() == 0 or out.numel() % PROBE_BLOCK:
+        raise ValueError(f"out must hold a positive multiple of {PROBE_BLOCK} values")
+    n_blocks = out.numel() // PROBE_BLOCK
+    check(lib().mhc_probe_mfma64(ctypes.c_void_p(out.data_ptr()), n_blocks, iters,
+                                 1 if with_valu else 0, _stream_ptr()))
+    flop = n_blocks * (PROBE_BLOCK // 64) * iters * 4 * 2048
+    if with_valu:
+        flop += out.numel() * iters * PROBE_FLOP_PER_ROUND
+    return flop
+
+
 def contract(plan: Plan, S: torch.Tensor, w_src: torch.Tensor, w_snk: torch.Tensor,
              method: str = "tree", with_scale: bool = False, with_pairs: bool = False,
              pairs=None):
