@@ -20,10 +20,14 @@ import os
 import sys
 import time
 
+# The multi-row group kernels take their tiles from the plans, so only the
+# persistent workgroups per compute unit remain to choose for them (0: as
+# many as stay resident, the library's choice); "group" forces the
+# one-row-per-lane kernels, whose items per tile are then tried too.
 DEFAULT_GRID = {
-    "kernel": ["auto", "group"],
-    "blocks_per_cu": [1, 2, 4],
-    "items_per_tile": [16, 64, 256],
+    "kernel": ["auto"],
+    "blocks_per_cu": [0, 1, 2],
+    "items_per_tile": [0],
 }
 
 
