@@ -267,6 +267,40 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_kernel(AdjointArgs a) {
   adjoint_finish(a, t, sb, acc_wk, n_singular, smem);
 }
 
+// Every member of dominator d against the lane's sink, pair by pair
+// (member_adjoint), for the lanes with `need`; weights added to the
+// partials of the update-tree kernel.
+template <int N>
+__device__ __forceinline__ void dominator_pairs(const AdjointArgs& a, const char* lds, char* glds,
+                                             int t, int sb, int d, int k, bool need, double2 gc,
+                                             double wk, double& acc_wk, uint32_t& n_singular) {
+  const PlanView& p = a.plan;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int term_d = uniform(p.dom_term[d]);
+  const uint32_t* rowoff_d = p.dom_rowoff + (size_t)d * p.sn;
+  const double wd = a.w_src[term_d];
+  double2 dd = member_adjoint<N>(p, lds, glds, rowoff_d, -1, -1, 0u, k, need, gc, wd * wk,
+                                 n_singular);
+  double val = need ? gc.x * dd.x + gc.y * dd.y : 0.0;
+  acc_wk += wd * val;
+  double s_i = wave_sum(wk * val);
+  if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + term_d) * a.n_sblk + sb] += s_i;
+  for (int gg = uniform(p.dom_grp[d]); gg < uniform(p.dom_grp[d + 1]); ++gg) {
+    const int fs = uniform(p.grp_fr[gg] >> 8), rs = uniform(p.grp_fr[gg] & 0xff);
+    for (int c = uniform(p.grp_ptr[gg]); c < uniform(p.grp_ptr[gg + 1]); ++c) {
+      const uint32_t crow = uniform(p.child_rowoff[c]);
+      const int cterm = uniform(p.child_term[c]);
+      const double wc = a.w_src[cterm];
+      dd = member_adjoint<N>(p, lds, glds, rowoff_d, fs, rs, crow, k, need, gc, wc * wk,
+                             n_singular);
+      val = need ? gc.x * dd.x + gc.y * dd.y : 0.0;
+      acc_wk += wc * val;
+      s_i = wave_sum(wk * val);
+      if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + cterm) * a.n_sblk + sb] += s_i;
+    }
+  }
+}
+
 // Update-tree adjoint: one (dominator, sink) at a time.  With G the
 // dominator's block f, x_m = G^-1 e_m, and the child c of flavour f that
 // replaces row r by s_c (z_c = s_c^T G^-1, rho_c = z_c[r]), the cofactor
@@ -278,9 +312,10 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_kernel(AdjointArgs a) {
 // Z_r = sum_{c in group r} w_c z_c (children of other flavours enter W
 // through their own rho_c; the rank-1 terms vanish on row r), and each
 // child adds w_c X_f det G_f x_r to its own row.  Pass A factorises the
-// blocks and forms W; pass B refactorises each block, solves its N unit
-// columns, the children's row vectors, and scatters.  A lane whose
-// dominator block has an exactly zero pivot takes every member pair by pair.
+// blocks and forms W; pass B refactorises each block transposed, inverts
+// it in place and adds each entry of the derivative once (rows of T).  A
+// lane whose dominator block has an exactly zero pivot takes every member
+// pair by pair (dominator_pairs).
 template <int N>
 __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) {
   extern __shared__ double2 smem[];
@@ -302,12 +337,18 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
   double acc_wk = 0.0;
   uint32_t n_singular = 0;
 
+  uint8_t* flag = a.dom_flag + ((size_t)t * a.n_sblk + sb) * p.n_dom;
   for (int d = wave; d < p.n_dom; d += kWavesPerBlock) {
     const int term_d = uniform(p.dom_term[d]);
     const double wd = a.w_src[term_d];
     const uint32_t* rowoff_d = p.dom_rowoff + (size_t)d * sn;
     const int g_begin = uniform(p.dom_grp[d]);
     const int g_end = uniform(p.dom_grp[d + 1]);
+    // the sink's column offsets are read again for every dominator: an
+    // opaque copy of k keeps their addresses from being hoisted out of the
+    // loop (F x N addresses live across it would spill)
+    int kk = k;
+    asm volatile("" : "+v"(kk));
 
     // pass A: block determinants and W
     double dre[kMaxAdjFlavors], dim[kMaxAdjFlavors];
@@ -324,7 +365,7 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
 #pragma unroll
       for (int n = 0; n < N; ++n) {
         ro[n] = rowoff_d[o + n];
-        co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + k];
+        co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + kk];
       }
       double gr[N][N], gi[N][N];
       int perm[N];
@@ -370,7 +411,17 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
       if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + term_d) * a.n_sblk + sb] = s_d;
     }
 
-    // pass B: scatter, block by block
+    // pass B, block by block: with x_m = G^-1 e_m, Z_r = the sum over the
+    // group of row r of w_c z_c and T[i][n] = W x_i[n] - sum_r Z_r[i] x_r[n],
+    // the dominator's row i takes B conj(T[i][n]) at column n, one add per
+    // entry; each child adds B conj(w_c x_r[n]) to its own row.  The block
+    // is factorised transposed (A = G^T, rows = the sink's columns,
+    // P A = L U) and V = U^-1 L^-1 holds x_i in its row i,
+    // x_i[perm[q]] = V[i][q], so a row of T needs no solve and no index
+    // that differs between lanes except the column addresses.
+    // B = gc * w_k * conj(X_f det_f) = gc * w_k * conj(D)
+    const double bre = wk * (gc.x * Dre + gc.y * Dim);
+    const double bim = wk * (gc.y * Dre - gc.x * Dim);
     g = g_begin;
 #pragma unroll
     for (int f = 0; f < kMaxAdjFlavors; ++f) {
@@ -378,9 +429,132 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
       const int o = p.off[f];
       int g_f_end = g;
       while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
-      // B = gc * w_k * conj(X_f det_f) = gc * w_k * conj(D)
-      const double bre = wk * (gc.x * Dre + gc.y * Dim);
-      const double bim = wk * (gc.y * Dre - gc.x * Dim);
+      uint32_t ro[N], co[N];
+#pragma unroll
+      for (int n = 0; n < N; ++n) {
+        ro[n] = rowoff_d[o + n];
+        co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + kk];
+      }
+      double vr[N][N], vi[N][N];
+      int perm[N];
+      {
+        double ddr, ddi;
+        bool z;
+        gather<N>(lds, co, ro, vr, vi);  // offsets add: vr[q][i] = G[i][q]
+        lu<N, true>(vr, vi, ddr, ddi, perm, z);
+        lu_inverse_v<N>(vr, vi);
+      }
+      uint32_t pcol[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        uint32_t v = co[0];
+#pragma unroll
+        for (int j = 1; j < N; ++j)
+          if (perm[q] == j) v = co[j];
+        pcol[q] = v;
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double tr[N], ti[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          tr[q] = Wre * vr[i][q] - Wim * vi[i][q];
+          ti[q] = Wre * vi[i][q] + Wim * vr[i][q];
+        }
+        for (int gg = g; gg < g_f_end; ++gg) {
+          const int r = uniform(p.grp_fr[gg] & 0xff);
+          double zr = 0.0, zi = 0.0;
+          for (int c = uniform(p.grp_ptr[gg]); c < uniform(p.grp_ptr[gg + 1]); ++c) {
+            const uint32_t crow = uniform(p.child_rowoff[c]);
+            const int cterm = uniform(p.child_term[c]);
+            const double wc = a.w_src[cterm];
+            // z_c[i] = sum_n s_c[n] x_i[n], s_c = the child's new row
+            double dr = 0.0, di = 0.0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+              const double2 sv = *reinterpret_cast<const double2*>(lds + crow + pcol[q]);
+              dr += sv.x * vr[i][q] - sv.y * vi[i][q];
+              di += sv.x * vi[i][q] + sv.y * vr[i][q];
+            }
+            zr += wc * dr;
+            zi += wc * di;
+            if (r == i) {
+              // rho_c = z_c[r]: the child's source weight, sum over sinks
+              // of w_k Re(gc conj(rho_c D)), and its own row
+              const double cr = dr * Dre - di * Dim, ci = dr * Dim + di * Dre;
+              const double s_c = wave_sum(fast ? wk * (gc.x * cr + gc.y * ci) : 0.0);
+              if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + cterm) * a.n_sblk + sb] = s_c;
+#pragma unroll
+              for (int q = 0; q < N; ++q)
+                if (fast)
+                  grad_add(glds, plane, crow, pcol[q], wc * (bre * vr[i][q] + bim * vi[i][q]),
+                           wc * (bim * vr[i][q] - bre * vi[i][q]));
+            }
+          }
+          // T[i] -= Z_r[i] x_r
+#pragma unroll
+          for (int rr = 0; rr < N; ++rr)
+            if (rr == r) {
+#pragma unroll
+              for (int q = 0; q < N; ++q) {
+                tr[q] -= zr * vr[rr][q] - zi * vi[rr][q];
+                ti[q] -= zr * vi[rr][q] + zi * vr[rr][q];
+              }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+          if (fast)
+            grad_add(glds, plane, ro[i], pcol[q], bre * tr[q] + bim * ti[q],
+                     bim * tr[q] - bre * ti[q]);
+      }
+      g = g_f_end;
+    }
+
+    // a lane whose dominator has a block with an exactly zero pivot: its
+    // member pairs go pair by pair in adjoint_tree_pairs_kernel
+    const bool need = valid && bad;
+    if (lane == 0) flag[d] = __builtin_amdgcn_ballot_w64(need) != 0 ? 1 : 0;
+  }
+  adjoint_finish(a, t, sb, acc_wk, n_singular, smem);
+}
+
+// The lanes of adjoint_tree_kernel whose dominator has a block with an
+// exactly zero pivot (no inverse, so no update formula): a workgroup per
+// (sink block, slice) as there, for the dominators that kernel flagged;
+// each lane refactorises the dominator's blocks as pass A did (same code,
+// same operands, so the same lanes find the zero pivot) and takes every
+// member pair by pair.  The results are added to that kernel's partials.
+// A workgroup without flagged dominators returns at once.
+template <int N>
+__global__ __launch_bounds__(kBlock, 2) void adjoint_tree_pairs_kernel(AdjointArgs a) {
+  extern __shared__ double2 smem[];
+  const PlanView& p = a.plan;
+  const int t = blockIdx.y;
+  const int sb = blockIdx.x;
+  const uint8_t* flag = a.dom_flag + ((size_t)t * a.n_sblk + sb) * p.n_dom;
+  int any = 0;
+  for (int d = threadIdx.x; d < p.n_dom; d += kBlock) any |= flag[d];
+  if (!__syncthreads_or(any)) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = uniform(threadIdx.x / kWave);
+  adjoint_stage(a, t, smem);
+  const char* lds = reinterpret_cast<const char*>(smem);
+  char* glds = reinterpret_cast<char*>(smem + p.M * lds_row(p.M));
+  const int k = adj_sink(sb, lane, a.n_sblk);
+  const bool valid = k < p.n_snk;
+  const double wk = valid ? a.w_snk[k] : 0.0;
+  const double2 gc = a.gC[t];
+  double acc_wk = 0.0;
+  uint32_t n_singular = 0;
+  for (int d = wave; d < p.n_dom; d += kWavesPerBlock) {
+    if (!uniform(flag[d])) continue;
+    const uint32_t* rowoff_d = p.dom_rowoff + (size_t)d * p.sn;
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < kMaxAdjFlavors; ++f) {
+      if (f >= p.F) continue;
+      const int o = p.off[f];
       uint32_t ro[N], co[N];
 #pragma unroll
       for (int n = 0; n < N; ++n) {
@@ -389,119 +563,39 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
       }
       double gr[N][N], gi[N][N];
       int perm[N];
-      double ddr, ddi;
+      double dr, di;
       bool z;
       gather<N>(lds, ro, co, gr, gi);
-      lu<N, true>(gr, gi, ddr, ddi, perm, z);
-      uint32_t prow[N];
-#pragma unroll
-      for (int m = 0; m < N; ++m) {
-        uint32_t v = ro[0];
-#pragma unroll
-        for (int j = 1; j < N; ++j)
-          if (perm[m] == j) v = ro[j];
-        prow[m] = v;
-      }
-      int gg = g;
-#pragma unroll
-      for (int m = 0; m < N; ++m) {
-        double xr[N], xi[N];
-        solve_unit<N>(gr, gi, perm, m, xr, xi);
-        // W (G^-1)^T: row m gets W x_m[n]; value v -> grad += B * conj(v)
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-          const double vr = Wre * xr[n] - Wim * xi[n];
-          const double vi = Wre * xi[n] + Wim * xr[n];
-          if (fast) grad_add(glds, plane, ro[m], co[n], bre * vr + bim * vi, bim * vr - bre * vi);
-        }
-        // the group that changes row m, if any (groups are sorted by row)
-        if (gg < g_f_end && uniform(p.grp_fr[gg] & 0xff) == m) {
-          double Zr[N], Zi[N];
-#pragma unroll
-          for (int j = 0; j < N; ++j) {
-            Zr[j] = 0.0;
-            Zi[j] = 0.0;
-          }
-          for (int c = uniform(p.grp_ptr[gg]); c < uniform(p.grp_ptr[gg + 1]); ++c) {
-            const uint32_t crow = uniform(p.child_rowoff[c]);
-            const int cterm = uniform(p.child_term[c]);
-            const double wc = a.w_src[cterm];
-            double br[N], bi[N];
-#pragma unroll
-            for (int n = 0; n < N; ++n) {
-              const double2 sv = *reinterpret_cast<const double2*>(lds + crow + co[n]);
-              br[n] = sv.x;
-              bi[n] = sv.y;
-            }
-            solve_row<N>(gr, gi, br, bi);       // z_c, as b with z[perm[j]] = b[j]
-            // rho_c = z_c[m]
-            double rr = 0.0, ri = 0.0;
-#pragma unroll
-            for (int j = 0; j < N; ++j)
-              if (perm[j] == m) {
-                rr = br[j];
-                ri = bi[j];
-              }
-            // the child's source weight: sum over sinks of w_k Re(gc conj(rho D))
-            const double cr = rr * Dre - ri * Dim, ci = rr * Dim + ri * Dre;
-            const double s_c = wave_sum(fast ? wk * (gc.x * cr + gc.y * ci) : 0.0);
-            if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + cterm) * a.n_sblk + sb] = s_c;
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-              Zr[j] += wc * br[j];
-              Zi[j] += wc * bi[j];
-            }
-            // the child's own row: w_c x_m[n] at (new row, column n)
-#pragma unroll
-            for (int n = 0; n < N; ++n) {
-              if (fast)
-                grad_add(glds, plane, crow, co[n], wc * (bre * xr[n] + bim * xi[n]),
-                         wc * (bim * xr[n] - bre * xi[n]));
-            }
-          }
-          // - Z_r x_r^T on the dominator's rows (Z in pivot order: entry j
-          // is original row perm[j])
-#pragma unroll
-          for (int j = 0; j < N; ++j)
-#pragma unroll
-            for (int n = 0; n < N; ++n) {
-              const double vr = -(Zr[j] * xr[n] - Zi[j] * xi[n]);
-              const double vi = -(Zr[j] * xi[n] + Zi[j] * xr[n]);
-              if (fast)
-                grad_add(glds, plane, prow[j], co[n], bre * vr + bim * vi, bim * vr - bre * vi);
-            }
-          ++gg;
-        }
-      }
-      g = g_f_end;
+      lu<N, true>(gr, gi, dr, di, perm, z);
+      bad = bad || z;
     }
-
-    // a dominator block with an exactly zero pivot: every member pair by pair
-    const bool need = valid && bad;
-    if (__builtin_amdgcn_ballot_w64(need) != 0) {
-      double2 dd = member_adjoint<N>(p, lds, glds, rowoff_d, -1, -1, 0u, k, need, gc, wd * wk,
-                                     n_singular);
-      double val = need ? gc.x * dd.x + gc.y * dd.y : 0.0;
-      acc_wk += wd * val;
-      double s_i = wave_sum(wk * val);
-      if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + term_d) * a.n_sblk + sb] += s_i;
-      for (int gg = g_begin; gg < g_end; ++gg) {
-        const int fs = uniform(p.grp_fr[gg] >> 8), rs = uniform(p.grp_fr[gg] & 0xff);
-        for (int c = uniform(p.grp_ptr[gg]); c < uniform(p.grp_ptr[gg + 1]); ++c) {
-          const uint32_t crow = uniform(p.child_rowoff[c]);
-          const int cterm = uniform(p.child_term[c]);
-          const double wc = a.w_src[cterm];
-          dd = member_adjoint<N>(p, lds, glds, rowoff_d, fs, rs, crow, k, need, gc, wc * wk,
-                                 n_singular);
-          val = need ? gc.x * dd.x + gc.y * dd.y : 0.0;
-          acc_wk += wc * val;
-          s_i = wave_sum(wk * val);
-          if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + cterm) * a.n_sblk + sb] += s_i;
-        }
-      }
-    }
+    dominator_pairs<N>(a, lds, glds, t, sb, d, k, valid && bad, gc, wk, acc_wk, n_singular);
   }
-  adjoint_finish(a, t, sb, acc_wk, n_singular, smem);
+  // sink weights (waves in a fixed order), singular blocks, grad S_t
+  __shared__ double red[kWavesPerBlock][kWave];
+  red[wave][lane] = acc_wk;
+  if (a.singular) {
+    uint32_t ns = n_singular;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) ns += __shfl_xor(ns, o, kWave);
+    if (lane == 0 && ns) atomicAdd(a.singular, (unsigned long long)ns);
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) v += red[w][threadIdx.x];
+    a.part_wsnk[(size_t)t * p.n_snk_pad + adj_sink(sb, threadIdx.x, a.n_sblk)] += v;
+  }
+  const int MM = p.M * p.M;
+  const double* re = reinterpret_cast<const double*>(smem + p.M * lds_row(p.M));
+  const double* im = re + p.M * lds_row(p.M);
+  double2* dst = a.part_gS + ((size_t)t * a.n_sblk + sb) * MM;
+  for (int e = threadIdx.x; e < MM; e += kBlock) {
+    const int q = (e / p.M) * lds_row(p.M) + e % p.M;
+    const double2 v = dst[e];
+    dst[e] = make_double2(v.x + re[q], v.y + im[q]);
+  }
 }
 
 // grad S[t][e] = sum over sink blocks of the partials (fixed order)
@@ -546,10 +640,16 @@ static hipError_t launch_adj_n(const AdjointArgs& a, bool tree, hipStream_t s) {
                         : reinterpret_cast<const void*>(&adjoint_kernel<N>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  if (tree)
-    hipLaunchKernelGGL(adjoint_tree_kernel<N>, grid, dim3(kBlock), lds, s, a);
-  else
+  if (!tree) {
     hipLaunchKernelGGL(adjoint_kernel<N>, grid, dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(adjoint_tree_kernel<N>, grid, dim3(kBlock), lds, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&adjoint_tree_pairs_kernel<N>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adjoint_tree_pairs_kernel<N>, grid, dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 

@@ -197,6 +197,8 @@ struct AdjointArgs {
   double* part_wsrc;              // [T][n_src][n_sblk]
   double* part_wsnk;              // [T][n_snk_pad]
   unsigned long long* singular;   // blocks with an exactly zero pivot (skipped)
+  uint8_t* dom_flag;              // [T][n_sblk][n_dom] update tree: dominators whose
+                                  // lanes need the pair-by-pair route
   int T, n_sblk;
 };
 

@@ -339,6 +339,51 @@ __device__ __forceinline__ void solve_row(const double (&gr)[N][N], const double
   }
 }
 
+// V = U^-1 L^-1 in place from the factors of lu<N, true> (P A = L U, unit L
+// below the diagonal, 1/U_mm on it), so that A^-1 = V P, that is
+// A^-1[a][perm[q]] = V[a][q].  First U^-1 over the upper triangle, column
+// by column (U^-1[i][j] = -(sum_{i<=k<j} U^-1[i][k] U[k][j]) / U_jj, rows
+// in increasing order so that U[k][j], k > i, is still unchanged), then
+// V L = U^-1 column by column from the right (V[:, j] = U^-1[:, j] -
+// sum_{k>j} V[:, k] L[k][j], with L[k][j] saved before column j is
+// overwritten).
+template <int N>
+__device__ __forceinline__ void lu_inverse_v(double (&gr)[N][N], double (&gi)[N][N]) {
+#pragma unroll
+  for (int j = 1; j < N; ++j)
+#pragma unroll
+    for (int i = 0; i < j; ++i) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int k = i; k < j; ++k) {
+        sr += gr[i][k] * gr[k][j] - gi[i][k] * gi[k][j];
+        si += gr[i][k] * gi[k][j] + gi[i][k] * gr[k][j];
+      }
+      gr[i][j] = -(sr * gr[j][j] - si * gi[j][j]);
+      gi[i][j] = -(sr * gi[j][j] + si * gr[j][j]);
+    }
+#pragma unroll
+  for (int j = N - 2; j >= 0; --j) {
+    double lr[N], li[N];
+#pragma unroll
+    for (int k = j + 1; k < N; ++k) {
+      lr[k] = gr[k][j];
+      li[k] = gi[k][j];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double vr = i <= j ? gr[i][j] : 0.0, vi = i <= j ? gi[i][j] : 0.0;
+#pragma unroll
+      for (int k = j + 1; k < N; ++k) {
+        vr = vr - gr[i][k] * lr[k] + gi[i][k] * li[k];
+        vi = vi - gr[i][k] * li[k] - gi[i][k] * lr[k];
+      }
+      gr[i][j] = vr;
+      gi[i][j] = vi;
+    }
+  }
+}
+
 __device__ __forceinline__ void masked_exchange_u32(uint64_t mask, uint32_t& a, uint32_t& b,
                                                    uint32_t& t) {
   uint64_t sv;

@@ -745,8 +745,9 @@ mhc_status mhc_contract_backward(mhc_plan* pl, int32_t method, int32_t T, const 
   const size_t MM = (size_t)pl->M * pl->M;
   const size_t b_gS = (size_t)T * n_sblk * MM * 16;
   const size_t b_src = ((size_t)T * pl->n_src * n_sblk * 8 + 255) & ~size_t(255);
-  const size_t b_snk = (size_t)T * pl->n_snk_pad * 8;
-  const size_t need = b_gS + b_src + b_snk;
+  const size_t b_snk = ((size_t)T * pl->n_snk_pad * 8 + 255) & ~size_t(255);
+  const size_t b_flag = method == MHC_UPDATE_TREE ? (size_t)T * n_sblk * pl->n_dom : 0;
+  const size_t need = b_gS + b_src + b_snk + b_flag;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (need > pl->adj_cap) {
     if (pl->adj_scratch) {
@@ -773,6 +774,7 @@ mhc_status mhc_contract_backward(mhc_plan* pl, int32_t method, int32_t T, const 
   a.part_gS = reinterpret_cast<double2*>(base);
   a.part_wsrc = reinterpret_cast<double*>(base + b_gS);
   a.part_wsnk = reinterpret_cast<double*>(base + b_gS + b_src);
+  a.dom_flag = b_flag ? reinterpret_cast<uint8_t*>(base + b_gS + b_src + b_snk) : nullptr;
   a.singular = pl->singular;
   a.T = T;
   a.n_sblk = n_sblk;

@@ -180,3 +180,42 @@ def test_tree_backward_with_singular_dominators():
     np.testing.assert_allclose(gws, ows, atol=1e-11 * np.abs(ows).max(), rtol=1e-9)
     np.testing.assert_allclose(gwk, owk, atol=1e-11 * np.abs(owk).max(), rtol=1e-9)
     assert plan.status()["n_singular_grad"] > 0
+
+
+@pytest.mark.parametrize("nf,M", [((1, 1), 12), ((4, 4), 12), ((5, 5), 14), ((7,), 12),
+                                  ((8, 8), 20), ((3, 3, 3), 14), ((2, 2, 2, 2), 12)])
+def test_tree_backward_block_sizes(nf, M):
+    # block sizes of the update-tree adjoint (one matrix per lane, blocks of
+    # one size n <= 8 in one to four flavours) against the gradient oracle
+    w = W.workload("mid", T=2, M=M, nf=nf, n_src=40, n_snk=70, branching=3, depth=3)
+    print(f"tree backward nf={nf} M={M}", flush=True)
+    plan, S, ws, wk = setup(w)
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal(w.T) + 1j * rng.standard_normal(w.T)
+    gS, gws, gwk = (x.cpu().numpy() for x in
+                    mhc.contract_backward(plan, S, ws, wk, torch.from_numpy(g), "tree"))
+    oS, ows, owk = og.vjp(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk, g)
+    np.testing.assert_allclose(gS, oS, atol=1e-11 * np.abs(oS).max(), rtol=1e-9)
+    np.testing.assert_allclose(gws, ows, atol=1e-11 * np.abs(ows).max(), rtol=1e-9)
+    np.testing.assert_allclose(gwk, owk, atol=1e-11 * np.abs(owk).max(), rtol=1e-9)
+
+
+def test_tree_backward_singular_for_some_sinks():
+    # a zero column of S: a dominator's blocks are singular only against the
+    # sinks that use that column, so within one wave some lanes take the
+    # update tree and the others the pair-by-pair route
+    w = W.workload("mid", T=2, M=12, nf=(3, 3), n_src=60, n_snk=130, branching=4, depth=2)
+    w.S[:, :, 5] = 0
+    plan, S, ws, wk = setup(w)
+    uses = (w.snk == 5).any(axis=1)
+    assert 0 < uses.sum() < len(w.snk)
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal(w.T) + 1j * rng.standard_normal(w.T)
+    gS, gws, gwk = (x.cpu().numpy() for x in
+                    mhc.contract_backward(plan, S, ws, wk, torch.from_numpy(g), "tree"))
+    oS, ows, owk = og.vjp(w.S, w.src, w.snk, w.nf, w.w_src, w.w_snk, g)
+    assert np.abs(oS[:, :, 5]).max() > 1e-3 * np.abs(oS).max()
+    np.testing.assert_allclose(gS, oS, atol=1e-11 * np.abs(oS).max(), rtol=1e-9)
+    np.testing.assert_allclose(gws, ows, atol=1e-11 * np.abs(ows).max(), rtol=1e-9)
+    np.testing.assert_allclose(gwk, owk, atol=1e-11 * np.abs(owk).max(), rtol=1e-9)
+    assert plan.status()["n_singular_grad"] > 0
