@@ -339,11 +339,11 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
 
   uint8_t* flag = a.dom_flag + ((size_t)t * a.n_sblk + sb) * p.n_dom;
   for (int d = wave; d < p.n_dom; d += kWavesPerBlock) {
-    const int term_d = uniform(p.dom_term[d]);
-    const double wd = a.w_src[term_d];
+    const int term_d = cload(p.dom_term, d);
+    const double wd = cload(a.w_src, term_d);
     const uint32_t* rowoff_d = p.dom_rowoff + (size_t)d * sn;
-    const int g_begin = uniform(p.dom_grp[d]);
-    const int g_end = uniform(p.dom_grp[d + 1]);
+    const int g_begin = cload(p.dom_grp, d);
+    const int g_end = cload(p.dom_grp, d + 1);
     // the sink's column offsets are read again for every dominator: an
     // opaque copy of k keeps their addresses from being hoisted out of the
     // loop (F x N addresses live across it would spill)
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
       uint32_t ro[N], co[N];
 #pragma unroll
       for (int n = 0; n < N; ++n) {
-        ro[n] = rowoff_d[o + n];
+        ro[n] = cload(rowoff_d, o + n);
         co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + kk];
       }
       double gr[N][N], gi[N][N];
@@ -373,19 +373,19 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
       gather<N>(lds, ro, co, gr, gi);
       lu<N, true>(gr, gi, dre[f], dim[f], perm, z);
       bad = bad || z;
-      for (; g < g_end && uniform(p.grp_fr[g] >> 8) == f; ++g) {
-        const int r = uniform(p.grp_fr[g] & 0xff);
+      for (; g < g_end && (cload(p.grp_fr, g) >> 8) == f; ++g) {
+        const int r = cload(p.grp_fr, g) & 0xff;
         double xr[N], xi[N];
         solve_unit<N>(gr, gi, perm, r, xr, xi);
-        for (int c = uniform(p.grp_ptr[g]); c < uniform(p.grp_ptr[g + 1]); ++c) {
-          const uint32_t crow = uniform(p.child_rowoff[c]);
-          const double wc = a.w_src[uniform(p.child_term[c])];
+        for (int c = cload(p.grp_ptr, g); c < cload(p.grp_ptr, g + 1); ++c) {
+          const uint32_t crow = cload(p.child_rowoff, c);
+          const double wc = cload(a.w_src, cload(p.child_term, c));
           double rr = 0.0, ri = 0.0;
 #pragma unroll
           for (int n = 0; n < N; ++n) {
             const double2 sv = *reinterpret_cast<const double2*>(lds + crow + co[n]);
-            rr += sv.x * xr[n] - sv.y * xi[n];
-            ri += sv.x * xi[n] + sv.y * xr[n];
+            rr = rr + sv.x * xr[n] - sv.y * xi[n];
+            ri = ri + sv.x * xi[n] + sv.y * xr[n];
           }
           Wre += wc * rr;
           Wim += wc * ri;
@@ -428,11 +428,11 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
       if (f >= F) continue;
       const int o = p.off[f];
       int g_f_end = g;
-      while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
+      while (g_f_end < g_end && (cload(p.grp_fr, g_f_end) >> 8) == f) ++g_f_end;
       uint32_t ro[N], co[N];
 #pragma unroll
       for (int n = 0; n < N; ++n) {
-        ro[n] = rowoff_d[o + n];
+        ro[n] = cload(rowoff_d, o + n);
         co[n] = p.snk_coloff[(size_t)(o + n) * p.n_snk_pad + kk];
       }
       double vr[N][N], vi[N][N];
@@ -462,19 +462,19 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
           ti[q] = Wre * vi[i][q] + Wim * vr[i][q];
         }
         for (int gg = g; gg < g_f_end; ++gg) {
-          const int r = uniform(p.grp_fr[gg] & 0xff);
+          const int r = cload(p.grp_fr, gg) & 0xff;
           double zr = 0.0, zi = 0.0;
-          for (int c = uniform(p.grp_ptr[gg]); c < uniform(p.grp_ptr[gg + 1]); ++c) {
-            const uint32_t crow = uniform(p.child_rowoff[c]);
-            const int cterm = uniform(p.child_term[c]);
-            const double wc = a.w_src[cterm];
+          for (int c = cload(p.grp_ptr, gg); c < cload(p.grp_ptr, gg + 1); ++c) {
+            const uint32_t crow = cload(p.child_rowoff, c);
+            const int cterm = cload(p.child_term, c);
+            const double wc = cload(a.w_src, cterm);
             // z_c[i] = sum_n s_c[n] x_i[n], s_c = the child's new row
             double dr = 0.0, di = 0.0;
 #pragma unroll
             for (int q = 0; q < N; ++q) {
               const double2 sv = *reinterpret_cast<const double2*>(lds + crow + pcol[q]);
-              dr += sv.x * vr[i][q] - sv.y * vi[i][q];
-              di += sv.x * vi[i][q] + sv.y * vr[i][q];
+              dr = dr + sv.x * vr[i][q] - sv.y * vi[i][q];
+              di = di + sv.x * vi[i][q] + sv.y * vr[i][q];
             }
             zr += wc * dr;
             zi += wc * di;
@@ -497,8 +497,8 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
             if (rr == r) {
 #pragma unroll
               for (int q = 0; q < N; ++q) {
-                tr[q] -= zr * vr[rr][q] - zi * vi[rr][q];
-                ti[q] -= zr * vi[rr][q] + zi * vr[rr][q];
+                tr[q] = tr[q] - zr * vr[rr][q] + zi * vi[rr][q];
+                ti[q] = ti[q] - zr * vi[rr][q] - zi * vr[rr][q];
               }
             }
         }

@@ -623,6 +623,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// A read of plan tables at a wave-uniform index through the constant
+// address space, so that it becomes a scalar load (the kernels write
+// global memory, and through a generic pointer the compiler keeps such
+// reads on the vector path, one memory latency per read).
+template <class T>
+__device__ __forceinline__ T cload(const T* ptr, long i) {
+  static_assert(sizeof(T) % 4 == 0, "read by 32-bit words");
+  const __attribute__((address_space(4))) uint32_t* q =
+      (const __attribute__((address_space(4))) uint32_t*)(ptr + i);
+  T v;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(T) / 4); ++w) d[w] = q[w];
+  return v;
+}
+
 __device__ __forceinline__ int uniform(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }

@@ -84,22 +84,6 @@ struct ChildInfo {
   double wc;       // its weight times the sign of its row permutation
 };
 
-// A read of plan tables at a wave-uniform index through the constant
-// address space, so that it becomes a scalar load (the kernels write
-// global memory, and through a generic pointer the compiler keeps such
-// reads on the vector path, one memory latency per read).
-template <class T>
-__device__ __forceinline__ T cload(const T* ptr, long i) {
-  static_assert(sizeof(T) % 4 == 0, "read by 32-bit words");
-  const __attribute__((address_space(4))) uint32_t* q =
-      (const __attribute__((address_space(4))) uint32_t*)(ptr + i);
-  T v;
-  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
-#pragma unroll
-  for (int w = 0; w < (int)(sizeof(T) / 4); ++w) d[w] = q[w];
-  return v;
-}
-
 // One chunk of slice t: tiles chunk, chunk + n_blk_t, ... of the method's
 // table.  MODE bit 0: accumulate A(t); bit 4: weighted-row aggregation of
 // each group's children (one dot per group, no per-child value).
