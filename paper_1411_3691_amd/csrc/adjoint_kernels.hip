@@ -30,6 +30,54 @@ namespace kern {
 
 constexpr int kMaxAdjFlavors = 4;
 
+// The sinks of one wave share most of their columns and, with them, most
+// of their pivot order, and LDS atomics of several lanes to one address
+// serialise.  After the inversion each lane rotates the columns of V (and
+// their addresses) by lane % kAdjSpread positions: the column index is a
+// summation label only, but at each step of a row's adds the lanes of a
+// wave then target up to kAdjSpread different columns.
+constexpr int kAdjSpread = 4;
+
+// V[i][q] <- V[i][(q + rho) % N], pcol[q] <- pcol[(q + rho) % N], rho =
+// lane % R, by selects (no register is indexed at run time).
+template <int N, int R>
+__device__ __forceinline__ void rotate_columns(double (&vr)[N][N], double (&vi)[N][N],
+                                               uint32_t (&pcol)[N], int lane) {
+  if constexpr (N > 1 && R > 1) {
+    const int rho = lane % R;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double tr[N], ti[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        tr[q] = vr[i][q];
+        ti[q] = vi[i][q];
+      }
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        double xr = tr[q], xi = ti[q];
+#pragma unroll
+        for (int s = 1; s < R; ++s) {
+          xr = rho == s ? tr[(q + s) % N] : xr;
+          xi = rho == s ? ti[(q + s) % N] : xi;
+        }
+        vr[i][q] = xr;
+        vi[i][q] = xi;
+      }
+    }
+    uint32_t tc[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) tc[q] = pcol[q];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      uint32_t c = tc[q];
+#pragma unroll
+      for (int s = 1; s < R; ++s) c = rho == s ? tc[(q + s) % N] : c;
+      pcol[q] = c;
+    }
+  }
+}
+
 // Sink of lane `lane` in sink block sb: the blocks take the sinks with a
 // stride of n_sblk, not 64 consecutive sinks.  Neighbouring sinks of a
 // tree-ordered list are siblings that share most of their column indices;
@@ -453,6 +501,7 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
           if (perm[q] == j) v = co[j];
         pcol[q] = v;
       }
+      rotate_columns<N, kAdjSpread>(vr, vi, pcol, lane);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         double tr[N], ti[N];
@@ -464,10 +513,16 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
         for (int gg = g; gg < g_f_end; ++gg) {
           const int r = cload(p.grp_fr, gg) & 0xff;
           double zr = 0.0, zi = 0.0;
-          for (int c = cload(p.grp_ptr, gg); c < cload(p.grp_ptr, gg + 1); ++c) {
-            const uint32_t crow = cload(p.child_rowoff, c);
-            const int cterm = cload(p.child_term, c);
-            const double wc = cload(a.w_src, cterm);
+          // the children's records, each read one child ahead
+          const int c_end = cload(p.grp_ptr, gg + 1);
+          int c = cload(p.grp_ptr, gg);
+          ChildRec next = cload(a.child_rec, c);
+          for (; c < c_end; ++c) {
+            const ChildRec cur = next;
+            next = cload(a.child_rec, c + 1);
+            const uint32_t crow = cur.crow;
+            const int cterm = cur.term;
+            const double wc = cur.w;
             // z_c[i] = sum_n s_c[n] x_i[n], s_c = the child's new row
             double dr = 0.0, di = 0.0;
 #pragma unroll
@@ -480,9 +535,9 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_kernel(AdjointArgs a) 
             zi += wc * di;
             if (r == i) {
               // rho_c = z_c[r]: the child's source weight, sum over sinks
-              // of w_k Re(gc conj(rho_c D)), and its own row
-              const double cr = dr * Dre - di * Dim, ci = dr * Dim + di * Dre;
-              const double s_c = wave_sum(fast ? wk * (gc.x * cr + gc.y * ci) : 0.0);
+              // of w_k Re(gc conj(rho_c D)) = Re(rho_c conj(B)), and its
+              // own row
+              const double s_c = wave_sum(fast ? dr * bre + di * bim : 0.0);
               if (lane == 0) a.part_wsrc[((size_t)t * p.n_src + cterm) * a.n_sblk + sb] = s_c;
 #pragma unroll
               for (int q = 0; q < N; ++q)
@@ -598,6 +653,19 @@ __global__ __launch_bounds__(kBlock, 2) void adjoint_tree_pairs_kernel(AdjointAr
   }
 }
 
+// The update tree's child records for one call: new row, term and weight.
+__global__ __launch_bounds__(kBlock) void child_records(const uint32_t* rowoff, const int32_t* term,
+                                                        const double* w_src, int n_children,
+                                                        ChildRec* out) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= n_children) return;
+  ChildRec r;
+  r.crow = rowoff[c];
+  r.term = term[c];
+  r.w = w_src[r.term];
+  out[c] = r;
+}
+
 // grad S[t][e] = sum over sink blocks of the partials (fixed order)
 __global__ __launch_bounds__(kBlock) void reduce_gS(const double2* part, int n_sblk, int MM,
                                                     int T, double2* gS) {
@@ -643,6 +711,12 @@ static hipError_t launch_adj_n(const AdjointArgs& a, bool tree, hipStream_t s) {
   if (!tree) {
     hipLaunchKernelGGL(adjoint_kernel<N>, grid, dim3(kBlock), lds, s, a);
     return hipGetLastError();
+  }
+  if (a.n_children > 0) {
+    hipLaunchKernelGGL(child_records, dim3((a.n_children + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       s, a.plan.child_rowoff, a.plan.child_term, a.w_src, a.n_children,
+                       a.child_rec);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(adjoint_tree_kernel<N>, grid, dim3(kBlock), lds, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;

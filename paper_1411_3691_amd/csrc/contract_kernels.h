@@ -187,6 +187,14 @@ hipError_t launch_batch_reduce(const ContractArgs* jobs, const int2* jt, int n, 
 namespace mhc {
 namespace kern {
 
+// A child of the update tree as the adjoint reads it: byte offset of its
+// new row in the LDS copy of S_t, its source term and that term's weight.
+struct ChildRec {
+  uint32_t crow;
+  int32_t term;
+  double w;
+};
+
 struct AdjointArgs {
   PlanView plan;
   const double2* S;               // [T][M][M]
@@ -199,7 +207,9 @@ struct AdjointArgs {
   unsigned long long* singular;   // blocks with an exactly zero pivot (skipped)
   uint8_t* dom_flag;              // [T][n_sblk][n_dom] update tree: dominators whose
                                   // lanes need the pair-by-pair route
-  int T, n_sblk;
+  ChildRec* child_rec;            // [n_children + 1] update tree: the children's
+                                  // records for this call (one spare, read ahead)
+  int T, n_sblk, n_children;
 };
 
 // Enqueues the adjoint (pair by pair, or by the source update tree) and the

@@ -746,8 +746,10 @@ mhc_status mhc_contract_backward(mhc_plan* pl, int32_t method, int32_t T, const 
   const size_t b_gS = (size_t)T * n_sblk * MM * 16;
   const size_t b_src = ((size_t)T * pl->n_src * n_sblk * 8 + 255) & ~size_t(255);
   const size_t b_snk = ((size_t)T * pl->n_snk_pad * 8 + 255) & ~size_t(255);
-  const size_t b_flag = method == MHC_UPDATE_TREE ? (size_t)T * n_sblk * pl->n_dom : 0;
-  const size_t need = b_gS + b_src + b_snk + b_flag;
+  const bool tree_m = method == MHC_UPDATE_TREE;
+  const size_t b_flag = tree_m ? ((size_t)T * n_sblk * pl->n_dom + 255) & ~size_t(255) : 0;
+  const size_t b_crec = tree_m ? ((size_t)pl->n_children + 1) * sizeof(mhc::kern::ChildRec) : 0;
+  const size_t need = b_gS + b_src + b_snk + b_flag + b_crec;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (need > pl->adj_cap) {
     if (pl->adj_scratch) {
@@ -774,7 +776,11 @@ mhc_status mhc_contract_backward(mhc_plan* pl, int32_t method, int32_t T, const 
   a.part_gS = reinterpret_cast<double2*>(base);
   a.part_wsrc = reinterpret_cast<double*>(base + b_gS);
   a.part_wsnk = reinterpret_cast<double*>(base + b_gS + b_src);
-  a.dom_flag = b_flag ? reinterpret_cast<uint8_t*>(base + b_gS + b_src + b_snk) : nullptr;
+  a.dom_flag = tree_m ? reinterpret_cast<uint8_t*>(base + b_gS + b_src + b_snk) : nullptr;
+  a.child_rec = tree_m ? reinterpret_cast<mhc::kern::ChildRec*>(base + b_gS + b_src + b_snk +
+                                                                b_flag)
+                       : nullptr;
+  a.n_children = tree_m ? pl->n_children : 0;
   a.singular = pl->singular;
   a.T = T;
   a.n_sblk = n_sblk;
