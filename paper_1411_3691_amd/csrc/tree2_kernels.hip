@@ -111,12 +111,12 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
     const int sb = uniform(item - d * a.n_sblk);
     const int k = sb * kWave + lane;
     const bool valid = k < q.n_sdom;
-    const int term_a = uniform(p.dom_term[d]);
-    const double wa = a.w_src[term_a];
+    const int term_a = cload(p.dom_term, d);
+    const double wa = cload(a.w_src, term_a);
     const double wb = valid ? a.w_snk[q.sdom_term[k]] : 0.0;
     const uint32_t* rowoff_d = p.dom_rowoff + (size_t)d * sn;
-    const int g_begin = uniform(p.dom_grp[d]);
-    const int g_end = uniform(p.dom_grp[d + 1]);
+    const int g_begin = cload(p.dom_grp, d);
+    const int g_end = cload(p.dom_grp, d + 1);
     const int sg_begin = q.sdom_grp[k];
     const int sg_end = q.sdom_grp[k + 1];
 
@@ -133,115 +133,137 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
 #pragma unroll
       for (int c = 0; c < N; ++c) co[c] = q.sdom_coloff[(size_t)(o + c) * pad + k];
 #pragma unroll
-      for (int m = 0; m < N; ++m) ro[m] = rowoff_d[o + m];
-      double gr[N][N], gi[N][N];
-      bool zero;
-      double dre, dim;
-      // Crout LU with column pivoting (G Q = L U): rows stay in place, co
-      // comes back in the factors' column order
-      lu_crout<N, true, kPartialPivot>(lds, ro, co, gr, gi, dre, dim, zero);
-      bad = bad || zero;
+      for (int m = 0; m < N; ++m) ro[m] = cload(rowoff_d, o + m);
+      // the block transposed (A = G^T, rows = the sink dominator's columns),
+      // P A = L U, then V = U^-1 L^-1 in place: G^-1[perm[j]][i] = V[i][j],
+      // so x_r = G^-1 e_r is row r of V with entry j at column pcol[j]
+      double vr[N][N], vi[N][N];
+      int perm[N];
       {
+        double dre, dim;
+        bool zero;
+        gather<N>(lds, co, ro, vr, vi);  // offsets add: vr[j][i] = G[i][j]
+        lu<N, true>(vr, vi, dre, dim, perm, zero);
+        lu_inverse_v<N>(vr, vi);
+        bad = bad || zero;
         const double tr = Pre * dre - Pim * dim;
         Pim = Pre * dim + Pim * dre;
         Pre = tr;
       }
-      // the source groups of flavour f (wave-uniform): x_r, rho_c
-      int g_f_end = g;
-      while (g_f_end < g_end && uniform(p.grp_fr[g_f_end] >> 8) == f) ++g_f_end;
-      for (int gg = g; gg < g_f_end; ++gg) {
-        const int r = uniform(p.grp_fr[gg] & 0xff);
-        const int c_begin = uniform(p.grp_ptr[gg]);
-        const int c_end = uniform(p.grp_ptr[gg + 1]);
-        // x_r in the factors' column order, the order of co
-        solve_unit_col<N>(gr, gi, r, gg, [&](const double (&xr)[N], const double (&xi)[N]) {
-          for (int c = c_begin; c < c_end; ++c) {
-            const uint32_t crow = uniform(p.child_rowoff[c]);
-            const double wc = a.w_src[uniform(p.child_term[c])];
-            double2 sv[N];
+      uint32_t pcol[N];
 #pragma unroll
-            for (int n = 0; n < N; ++n)
-              sv[n] = *reinterpret_cast<const double2*>(lds + crow + co[n]);
-            __builtin_amdgcn_sched_barrier(0);
-            double rr = 0.0, ri = 0.0;
+      for (int j = 0; j < N; ++j) {
+        uint32_t v = co[0];
 #pragma unroll
-            for (int n = 0; n < N; ++n) {
-              rr += sv[n].x * xr[n] - sv[n].y * xi[n];
-              ri += sv[n].x * xi[n] + sv[n].y * xr[n];
-            }
-            Rre += wc * rr;
-            Rim += wc * ri;
-          }
-        });
+        for (int n = 1; n < N; ++n)
+          if (perm[j] == n) v = co[n];
+        pcol[j] = v;
       }
-      // this lane's sink groups in flavour f: y_c, sigma_d, and where the
-      // source dominator has children in this block, q_d = G^-1 v_d and the
-      // same-block pair terms (source loops inside are wave-uniform)
+      // the source groups of flavour f (wave-uniform): sum_c w_c rho_c =
+      // sigma . x_r with sigma = sum_c w_c s_c, s_c the child's new row
+      int g_f_end = g;
+      while (g_f_end < g_end && (cload(p.grp_fr, g_f_end) >> 8) == f) ++g_f_end;
+      for (int gg = g; gg < g_f_end; ++gg) {
+        const int r = cload(p.grp_fr, gg) & 0xff;
+        double sr[N], si[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          sr[j] = 0.0;
+          si[j] = 0.0;
+        }
+        for (int c = cload(p.grp_ptr, gg); c < cload(p.grp_ptr, gg + 1); ++c) {
+          const uint32_t crow = cload(p.child_rowoff, c);
+          const double wc = cload(a.w_src, cload(p.child_term, c));
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            const double2 sv = *reinterpret_cast<const double2*>(lds + crow + pcol[j]);
+            sr[j] += wc * sv.x;
+            si[j] += wc * sv.y;
+          }
+        }
+#pragma unroll
+        for (int rr = 0; rr < N; ++rr)
+          if (rr == r) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+              Rre = Rre + sr[j] * vr[rr][j] - si[j] * vi[rr][j];
+              Rim = Rim + sr[j] * vi[rr][j] + si[j] * vr[rr][j];
+            }
+          }
+      }
+      // this lane's sink groups in flavour f (column cc -> new column v_d):
+      // with p = G^-1 v_d (p[j] its entry perm[j]), sigma_d = y_cc . v_d =
+      // p at perm[j] == cc; where the source dominator has children in
+      // this block, the same-block pairs take kappa = G^-1[cc][r] and
+      // beta - alpha = s_c . p - S[new row][new column]
       const bool src_kids = g_f_end > g;
       int sg_f = sg;
       while (sg_f < sg_end && (q.sgrp_fc[sg_f] >> 8) == f) ++sg_f;
       for (int h = sg; h < sg_f; ++h) {
         const int cc = q.sgrp_fc[h] & 0xff;
-        // y_c = e_c^T G^-1 = (Q^T e_c)^T U^-1 L^-1: the unit vector sits at
-        // the factors' position of original column cc; y comes out in the
-        // original row order
-        const uint32_t ccol = q.sdom_coloff[(size_t)(o + cc) * pad + k];
-        double br[N], bi[N];
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          br[j] = (co[j] == ccol) ? 1.0 : 0.0;
-          bi[j] = 0.0;
-        }
-        solve_row<N>(gr, gi, br, bi);
         for (int ch = q.sgrp_ptr[h]; ch < q.sgrp_ptr[h + 1]; ++ch) {
           const uint32_t col = q.schild_coloff[ch];
           const double wd = a.w_snk[q.schild_term[ch]];
-          // v_d: the new column at the dominator's rows
-          double vr[N], vi[N];
+          double tr[N], ti[N];
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            const double2 v = *reinterpret_cast<const double2*>(lds + ro[i] + col);
+            tr[i] = v.x;
+            ti[i] = v.y;
+          }
+          double pr[N], pi[N];
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            double xr = 0.0, xi = 0.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+              xr = xr + vr[i][j] * tr[i] - vi[i][j] * ti[i];
+              xi = xi + vr[i][j] * ti[i] + vi[i][j] * tr[i];
+            }
+            pr[j] = xr;
+            pi[j] = xi;
+          }
           double sr = 0.0, si = 0.0;
 #pragma unroll
-          for (int m = 0; m < N; ++m) {
-            const double2 v = *reinterpret_cast<const double2*>(lds + ro[m] + col);
-            vr[m] = v.x;
-            vi[m] = v.y;
-            sr += br[m] * v.x - bi[m] * v.y;
-            si += br[m] * v.y + bi[m] * v.x;
-          }
+          for (int j = 0; j < N; ++j)
+            if (perm[j] == cc) {
+              sr = pr[j];
+              si = pi[j];
+            }
           Sre += wd * sr;
           Sim += wd * si;
           if (!src_kids) continue;
-          solve_col<N>(gr, gi, vr, vi);   // q_d = G^-1 v_d, in the factors' column order
           double tre = 0.0, tim = 0.0;
           for (int gg = g; gg < g_f_end; ++gg) {
-            const int r = uniform(p.grp_fr[gg] & 0xff);
-            // kappa = (G^-1)[cc][r] = y_c[r] (y in the original row order)
+            const int r = cload(p.grp_fr, gg) & 0xff;
             double kr = 0.0, ki = 0.0;
 #pragma unroll
-            for (int m = 0; m < N; ++m)
-              if (m == r) {
-                kr = br[m];
-                ki = bi[m];
+            for (int rr = 0; rr < N; ++rr)
+              if (rr == r) {
+#pragma unroll
+                for (int j = 0; j < N; ++j)
+                  if (perm[j] == cc) {
+                    kr = vr[rr][j];
+                    ki = vi[rr][j];
+                  }
               }
             double ure = 0.0, uim = 0.0;
-            const int c_begin = uniform(p.grp_ptr[gg]);
-            const int c_end = uniform(p.grp_ptr[gg + 1]);
-            for (int c = c_begin; c < c_end; ++c) {
-              const uint32_t crow = uniform(p.child_rowoff[c]);
-              const double wc = a.w_src[uniform(p.child_term[c])];
-              // beta - alpha = s_c . q_d - S[new row][new column]
+            for (int c = cload(p.grp_ptr, gg); c < cload(p.grp_ptr, gg + 1); ++c) {
+              const uint32_t crow = cload(p.child_rowoff, c);
+              const double wc = cload(a.w_src, cload(p.child_term, c));
               const double2 al = *reinterpret_cast<const double2*>(lds + crow + col);
               double bre = -al.x, bim = -al.y;
 #pragma unroll
-              for (int n = 0; n < N; ++n) {
-                const double2 sv = *reinterpret_cast<const double2*>(lds + crow + co[n]);
-                bre += sv.x * vr[n] - sv.y * vi[n];
-                bim += sv.x * vi[n] + sv.y * vr[n];
+              for (int j = 0; j < N; ++j) {
+                const double2 sv = *reinterpret_cast<const double2*>(lds + crow + pcol[j]);
+                bre = bre + sv.x * pr[j] - sv.y * pi[j];
+                bim = bim + sv.x * pi[j] + sv.y * pr[j];
               }
               ure += wc * bre;
               uim += wc * bim;
             }
-            tre += kr * ure - ki * uim;
-            tim += kr * uim + ki * ure;
+            tre = tre + kr * ure - ki * uim;
+            tim = tim + kr * uim + ki * ure;
           }
           Kre += wd * tre;
           Kim += wd * tim;
