@@ -78,6 +78,8 @@ struct ContractArgs {
   double2* pair_det;              // [T][n_src][n_snk] or null
   unsigned long long* fallback;   // fallback counter or null
   int T, n_items, n_blk_t, n_sblk;
+  int tab_rows;                   // two-sided: rows of each wave's LDS table of
+                                  // aggregated child rows (0: none)
   double2* C;                     // outputs, read by the batch reduction only
   double* A;
 };

@@ -27,6 +27,7 @@ struct mhc_plan {
   int32_t n = 0;          // largest flavour block
   bool uniform_n = true;  // every flavour block has size n
   int32_t n_dom = 0, n_groups = 0, n_children = 0;
+  int32_t max_dom_groups = 0;          // most groups of one dominator
   std::vector<int32_t> off;
   void* dev_tables = nullptr;          // one allocation for every table
   mhc::kern::PlanView view{};
@@ -64,6 +65,9 @@ constexpr int kTargetBlocks = 4096;
 // The LDS of one workgroup of the multi-row group kernels: 160 KiB less
 // 1 KiB for their static arrays.
 constexpr size_t kRowsLdsLimit = 159 * 1024;
+// LDS of a two-sided workgroup with its aggregated-row tables, at most
+// (two workgroups per compute unit).
+constexpr size_t kTree2LdsLimit = 80 * 1024;
 
 mhc_status hip_fail(hipError_t e, const char* where) {
   return fail(MHC_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
@@ -277,6 +281,8 @@ mhc_status mhc_plan_create(const mhc_tree* tree, const mhc_terms* snk,
   pl->n_dom = (int32_t)tree->dom_order.size();
   pl->n_groups = (int32_t)tree->grp_f.size();
   pl->n_children = (int32_t)tree->grp_child.size();
+  for (int k = 0; k < pl->n_dom; ++k)
+    pl->max_dom_groups = std::max(pl->max_dom_groups, tree->dom_grp[k + 1] - tree->dom_grp[k]);
   pl->snk_idx = snk->idx;
   pl->set_edges = tree->set_edges;
 
@@ -655,6 +661,13 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
   a.n_blk_t = n_blk_t;
   a.n_sblk = n_sblk;
   a.snk = pl->view_snk;
+  if (two) {
+    // per wave, the source dominator's aggregated child rows (one row of M
+    // entries per group) beside the slice, where the LDS holds them
+    const size_t tab = (size_t)mhc::kern::kWavesPerBlock * pl->max_dom_groups * pl->M * 16;
+    a.tab_rows = mhc::kern::lds_slice_bytes(pl->M) + tab <= kTree2LdsLimit ? pl->max_dom_groups
+                                                                             : 0;
+  }
   if (two)
     e = mhc::kern::launch_contract_two_sided(a, pl->n, static_cast<double2*>(C),
                                              reinterpret_cast<hipStream_t>(stream));

@@ -35,6 +35,7 @@
 #include <cstdint>
 
 #include "contract_kernels.h"
+#include "group_device.h"
 #include "lu_device.h"
 
 namespace mhc {
@@ -85,7 +86,7 @@ __device__ __forceinline__ void block_det2(const char* lds, const uint32_t* rowo
   lu<N, false>(gr, gi, dre, dim, perm, z);
 }
 
-template <int N>
+template <int N, bool TAB>
 __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int chunk,
                                                double2* smem) {
   const PlanView& p = a.plan;
@@ -119,6 +120,30 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
     const int g_end = cload(p.dom_grp, d + 1);
     const int sg_begin = q.sdom_grp[k];
     const int sg_end = q.sdom_grp[k + 1];
+
+    // TAB: row l of this wave's table holds A_g = sum_c w_c S[new row of
+    // c][:] for group g = g_begin + l (the source dominator's groups); the
+    // previous item's rows were read by this wave only, in program order
+    char* tab = reinterpret_cast<char*>(smem) + lds_slice_bytes(p.M) +
+                (size_t)wave * a.tab_rows * p.M * 16;
+    if (TAB) {
+      for (int gg = g_begin; gg < g_end; ++gg) {
+        const int c0 = cload(p.grp_ptr, gg), c1 = cload(p.grp_ptr, gg + 1);
+        for (int col = lane; col < p.M; col += kWave) {
+          double xr = 0.0, xi = 0.0;
+          for (int c = c0; c < c1; ++c) {
+            const uint32_t crow = cload(p.child_rowoff, c);
+            const double wc = cload(a.w_src, cload(p.child_term, c));
+            const double2 v = *reinterpret_cast<const double2*>(lds + crow + col * 16);
+            xr += wc * v.x;
+            xi += wc * v.y;
+          }
+          *reinterpret_cast<double2*>(tab + ((size_t)(gg - g_begin) * p.M + col) * 16) =
+              make_double2(xr, xi);
+        }
+      }
+      wave_lds_sync();
+    }
 
     double Pre = 1.0, Pim = 0.0;     // prod_f det G_f
     double Rre = 0.0, Rim = 0.0;     // sum_c w_c rho_c
@@ -166,19 +191,29 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
       for (int gg = g; gg < g_f_end; ++gg) {
         const int r = cload(p.grp_fr, gg) & 0xff;
         double sr[N], si[N];
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          sr[j] = 0.0;
-          si[j] = 0.0;
-        }
-        for (int c = cload(p.grp_ptr, gg); c < cload(p.grp_ptr, gg + 1); ++c) {
-          const uint32_t crow = cload(p.child_rowoff, c);
-          const double wc = cload(a.w_src, cload(p.child_term, c));
+        if (TAB) {
+          const char* arow = tab + (size_t)(gg - g_begin) * p.M * 16;
 #pragma unroll
           for (int j = 0; j < N; ++j) {
-            const double2 sv = *reinterpret_cast<const double2*>(lds + crow + pcol[j]);
-            sr[j] += wc * sv.x;
-            si[j] += wc * sv.y;
+            const double2 sv = *reinterpret_cast<const double2*>(arow + pcol[j]);
+            sr[j] = sv.x;
+            si[j] = sv.y;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            sr[j] = 0.0;
+            si[j] = 0.0;
+          }
+          for (int c = cload(p.grp_ptr, gg); c < cload(p.grp_ptr, gg + 1); ++c) {
+            const uint32_t crow = cload(p.child_rowoff, c);
+            const double wc = cload(a.w_src, cload(p.child_term, c));
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+              const double2 sv = *reinterpret_cast<const double2*>(lds + crow + pcol[j]);
+              sr[j] += wc * sv.x;
+              si[j] += wc * sv.y;
+            }
           }
         }
 #pragma unroll
@@ -248,19 +283,33 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
                   }
               }
             double ure = 0.0, uim = 0.0;
-            for (int c = cload(p.grp_ptr, gg); c < cload(p.grp_ptr, gg + 1); ++c) {
-              const uint32_t crow = cload(p.child_rowoff, c);
-              const double wc = cload(a.w_src, cload(p.child_term, c));
-              const double2 al = *reinterpret_cast<const double2*>(lds + crow + col);
-              double bre = -al.x, bim = -al.y;
+            if (TAB) {
+              // sum_c w_c (s_c . p - S[new row][new column]) = A_g . p - A_g[col]
+              const char* arow = tab + (size_t)(gg - g_begin) * p.M * 16;
+              const double2 al = *reinterpret_cast<const double2*>(arow + col);
+              ure = -al.x;
+              uim = -al.y;
 #pragma unroll
               for (int j = 0; j < N; ++j) {
-                const double2 sv = *reinterpret_cast<const double2*>(lds + crow + pcol[j]);
-                bre = bre + sv.x * pr[j] - sv.y * pi[j];
-                bim = bim + sv.x * pi[j] + sv.y * pr[j];
+                const double2 sv = *reinterpret_cast<const double2*>(arow + pcol[j]);
+                ure = ure + sv.x * pr[j] - sv.y * pi[j];
+                uim = uim + sv.x * pi[j] + sv.y * pr[j];
               }
-              ure += wc * bre;
-              uim += wc * bim;
+            } else {
+              for (int c = cload(p.grp_ptr, gg); c < cload(p.grp_ptr, gg + 1); ++c) {
+                const uint32_t crow = cload(p.child_rowoff, c);
+                const double wc = cload(a.w_src, cload(p.child_term, c));
+                const double2 al = *reinterpret_cast<const double2*>(lds + crow + col);
+                double bre = -al.x, bim = -al.y;
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                  const double2 sv = *reinterpret_cast<const double2*>(lds + crow + pcol[j]);
+                  bre = bre + sv.x * pr[j] - sv.y * pi[j];
+                  bim = bim + sv.x * pi[j] + sv.y * pr[j];
+                }
+                ure += wc * bre;
+                uim += wc * bim;
+              }
             }
             tre = tre + kr * ure - ki * uim;
             tim = tim + kr * uim + ki * ure;
@@ -373,20 +422,26 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
   }
 }
 
-template <int N>
+template <int N, bool TAB>
 __global__ __launch_bounds__(kBlock, 2) void contract_two_sided_kernel(ContractArgs a) {
   extern __shared__ double2 smem[];
-  two_sided_tile<N>(a, blockIdx.y, blockIdx.x, smem);
+  two_sided_tile<N, TAB>(a, blockIdx.y, blockIdx.x, smem);
 }
 
 template <int N>
 static hipError_t launch_two_sided_n(const ContractArgs& a, hipStream_t s) {
   dim3 grid(a.n_blk_t, a.T);
-  const size_t lds = lds_slice_bytes(a.plan.M);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&contract_two_sided_kernel<N>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const bool tab = a.tab_rows > 0;
+  const size_t lds = lds_slice_bytes(a.plan.M) +
+                     (tab ? (size_t)kWavesPerBlock * a.tab_rows * a.plan.M * 16 : 0);
+  const void* fn = tab ? reinterpret_cast<const void*>(&contract_two_sided_kernel<N, true>)
+                       : reinterpret_cast<const void*>(&contract_two_sided_kernel<N, false>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((contract_two_sided_kernel<N>), grid, dim3(kBlock), lds, s, a);
+  if (tab)
+    hipLaunchKernelGGL((contract_two_sided_kernel<N, true>), grid, dim3(kBlock), lds, s, a);
+  else
+    hipLaunchKernelGGL((contract_two_sided_kernel<N, false>), grid, dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
