@@ -167,7 +167,10 @@ __device__ __forceinline__ double pivot_key(double re, double im, int m) {
 // move only where a lane needs it (a step no lane pivots in is skipped).
 constexpr double kThreshold = 0.1;
 
-template <int N, bool KEEP, bool PIVOT = true, bool THRESH = false>
+// TAGS (with KEEP): perm holds a caller's tag per row on entry (a row's
+// LDS offset, say) and the tags move with their rows, so that perm[m] is
+// the tag of the row now in position m.
+template <int N, bool KEEP, bool PIVOT = true, bool THRESH = false, bool TAGS = false>
 __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
                                    double& dre, double& dim, int (&perm)[N],
                                    bool& zero_pivot) {
@@ -175,7 +178,7 @@ __device__ __forceinline__ void lu(double (&gr)[N][N], double (&gi)[N][N],
   double sre = 1.0, sim = 0.0;
   bool neg = false;
   zero_pivot = false;
-  if (KEEP) {
+  if (KEEP && !TAGS) {
 #pragma unroll
     for (int m = 0; m < N; ++m) perm[m] = m;
   }

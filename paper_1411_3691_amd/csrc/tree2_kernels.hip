@@ -163,26 +163,21 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
       // P A = L U, then V = U^-1 L^-1 in place: G^-1[perm[j]][i] = V[i][j],
       // so x_r = G^-1 e_r is row r of V with entry j at column pcol[j]
       double vr[N][N], vi[N][N];
-      int perm[N];
+      // the column offsets ride along with the rows of A: pcol[j] is the
+      // offset of column perm[j]
+      int pcol[N];
       {
         double dre, dim;
         bool zero;
         gather<N>(lds, co, ro, vr, vi);  // offsets add: vr[j][i] = G[i][j]
-        lu<N, true>(vr, vi, dre, dim, perm, zero);
+#pragma unroll
+        for (int j = 0; j < N; ++j) pcol[j] = (int)co[j];
+        lu<N, true, true, false, true>(vr, vi, dre, dim, pcol, zero);
         lu_inverse_v<N>(vr, vi);
         bad = bad || zero;
         const double tr = Pre * dre - Pim * dim;
         Pim = Pre * dim + Pim * dre;
         Pre = tr;
-      }
-      uint32_t pcol[N];
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        uint32_t v = co[0];
-#pragma unroll
-        for (int n = 1; n < N; ++n)
-          if (perm[j] == n) v = co[n];
-        pcol[j] = v;
       }
       // the source groups of flavour f (wave-uniform): sum_c w_c rho_c =
       // sigma . x_r with sigma = sum_c w_c s_c, s_c the child's new row
@@ -228,14 +223,17 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
       }
       // this lane's sink groups in flavour f (column cc -> new column v_d):
       // with p = G^-1 v_d (p[j] its entry perm[j]), sigma_d = y_cc . v_d =
-      // p at perm[j] == cc; where the source dominator has children in
+      // p at perm[j] == cc, the position whose column offset pcol[j] is
+      // cc's; where the source dominator has children in
       // this block, the same-block pairs take kappa = G^-1[cc][r] and
       // beta - alpha = s_c . p - S[new row][new column]
       const bool src_kids = g_f_end > g;
       int sg_f = sg;
       while (sg_f < sg_end && (q.sgrp_fc[sg_f] >> 8) == f) ++sg_f;
       for (int h = sg; h < sg_f; ++h) {
+        // the changed column's offset: pcol[j] == ccol marks its position
         const int cc = q.sgrp_fc[h] & 0xff;
+        const uint32_t ccol = q.sdom_coloff[(size_t)(o + cc) * pad + k];
         for (int ch = q.sgrp_ptr[h]; ch < q.sgrp_ptr[h + 1]; ++ch) {
           const uint32_t col = q.schild_coloff[ch];
           const double wd = a.w_snk[q.schild_term[ch]];
@@ -261,7 +259,7 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
           double sr = 0.0, si = 0.0;
 #pragma unroll
           for (int j = 0; j < N; ++j)
-            if (perm[j] == cc) {
+            if ((uint32_t)pcol[j] == ccol) {
               sr = pr[j];
               si = pi[j];
             }
@@ -277,7 +275,7 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
               if (rr == r) {
 #pragma unroll
                 for (int j = 0; j < N; ++j)
-                  if (perm[j] == cc) {
+                  if ((uint32_t)pcol[j] == ccol) {
                     kr = vr[rr][j];
                     ki = vi[rr][j];
                   }
