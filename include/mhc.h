@@ -260,8 +260,9 @@ mhc_status mhc_contract(mhc_plan* plan, int32_t method, int32_t T,
  * (2 MiB per device, held until the process ends) instead of a buffer
  * grown on the plan.  It calls no hipMalloc or hipFree; its first call on a
  * device only looks up that array's address there.  Every valid T fits (the
- * partials take at most 3 * (4096 + T) doubles); a call that would need
- * more returns MHC_E_UNSUPPORTED.  All calls on one device share the array
+ * partials take at most 3 * (4096 + T) doubles, 3.5 * (4096 + T) with
+ * MHC_UPDATE_TREE2, whose workgroups also leave a flag each); a call that
+ * would need more returns MHC_E_UNSUPPORTED.  All calls on one device share the array
  * and its contents: calls that overlap in time on one device (different
  * streams, threads or plans) race.  Arguments, methods and errors as for
  * mhc_contract. */

@@ -92,6 +92,12 @@ struct BatchArgs {
   int n_tiles;
 };
 
+// LDS of a two-sided workgroup with its aggregated-row tables and its
+// threads' running sums, at most (two workgroups per compute unit), and
+// the bytes of those sums (256 threads x 4 complex numbers).
+constexpr size_t kTwoSidedLdsLimit = 80 * 1024;
+constexpr size_t kTwoSidedSlotBytes = 256 * 4 * 16;
+
 // Flavour blocks supported by the pair-determinant test hook.
 constexpr int kPairFlavors = 4;
 

@@ -65,9 +65,6 @@ constexpr int kTargetBlocks = 4096;
 // The LDS of one workgroup of the multi-row group kernels: 160 KiB less
 // 1 KiB for their static arrays.
 constexpr size_t kRowsLdsLimit = 159 * 1024;
-// LDS of a two-sided workgroup with its aggregated-row tables, at most
-// (two workgroups per compute unit).
-constexpr size_t kTree2LdsLimit = 80 * 1024;
 
 mhc_status hip_fail(hipError_t e, const char* where) {
   return fail(MHC_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
@@ -626,7 +623,8 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
     n_blk_t = (int)std::min<long long>(n_blk_t,
                                        (n_items + waves_per_block - 1) / waves_per_block);
   n_blk_t = std::max(1, n_blk_t);
-  const size_t need = (size_t)T * n_blk_t * 3;
+  // two-sided: a flag per workgroup after the partials (ints, two per double)
+  const size_t need = (size_t)T * n_blk_t * 3 + (two ? ((size_t)T * n_blk_t + 1) / 2 : 0);
   if (fixed) {
     if (need > fixed_cap)
       return fail(MHC_E_UNSUPPORTED,
@@ -665,8 +663,10 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
     // per wave, the source dominator's aggregated child rows (one row of M
     // entries per group) beside the slice, where the LDS holds them
     const size_t tab = (size_t)mhc::kern::kWavesPerBlock * pl->max_dom_groups * pl->M * 16;
-    a.tab_rows = mhc::kern::lds_slice_bytes(pl->M) + tab <= kTree2LdsLimit ? pl->max_dom_groups
-                                                                             : 0;
+    a.tab_rows = mhc::kern::lds_slice_bytes(pl->M) + tab + mhc::kern::kTwoSidedSlotBytes <=
+                         mhc::kern::kTwoSidedLdsLimit
+                     ? pl->max_dom_groups
+                     : 0;
   }
   if (two)
     e = mhc::kern::launch_contract_two_sided(a, pl->n, static_cast<double2*>(C),

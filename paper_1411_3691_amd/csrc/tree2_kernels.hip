@@ -86,7 +86,30 @@ __device__ __forceinline__ void block_det2(const char* lds, const uint32_t* rowo
   lu<N, false>(gr, gi, dre, dim, perm, z);
 }
 
-template <int N, bool TAB>
+static_assert(kTwoSidedSlotBytes == (size_t)kBlock * 4 * 16, "one slot per thread");
+
+// A thread's running sums (four complex numbers): in its LDS slot (PARK),
+// or in registers where the LDS has no room for the slots.
+template <bool PARK>
+struct RunningSums {
+  double2* slot;
+  __device__ double2 get(int i) const { return slot[i]; }
+  __device__ void set(int i, double2 v) { slot[i] = v; }
+};
+template <>
+struct RunningSums<false> {
+  double2 r[4];
+  __device__ double2 get(int i) const { return r[i]; }
+  __device__ void set(int i, double2 v) { r[i] = v; }
+};
+
+// Per (slice, chunk): whether a lane of the chunk met a block with an
+// exactly zero pivot; ints after the workgroup partials.
+__device__ __forceinline__ int* two_sided_flags(const ContractArgs& a) {
+  return reinterpret_cast<int*>(a.partial + (size_t)a.T * a.n_blk_t * 3);
+}
+
+template <int N, bool TAB, bool PARK>
 __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int chunk,
                                                double2* smem) {
   const PlanView& p = a.plan;
@@ -100,8 +123,18 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
   __syncthreads();
   const char* lds = reinterpret_cast<const char*>(smem);
 
-  double acc_re = 0.0, acc_im = 0.0;
-  uint32_t n_fallback = 0;
+  // Each lane's running sums over the blocks of an item live in LDS between
+  // the blocks (PARK: a slot of four complex numbers per thread, after the
+  // slice and the tables), so that no register holds them through a
+  // factorisation: 0 the product of the block dets, 1 sum_c w_c rho_c,
+  // 2 sum_d w_d sigma_d, 3 the same-block pair sum.
+  RunningSums<PARK> sums;
+  if constexpr (PARK)
+    sums.slot = reinterpret_cast<double2*>(reinterpret_cast<char*>(smem) + lds_slice_bytes(p.M) +
+                                           (size_t)kWavesPerBlock * a.tab_rows * p.M * 16) +
+                (size_t)threadIdx.x * 4;
+  double acc_re = 0.0, acc_im = 0.0;  // the lane's total over its items
+  bool any_bad = false;  // wave-uniform
   const int F = p.F;
   const int sn = p.sn;
   const int pad = q.n_sdom_pad;
@@ -114,12 +147,12 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
     const bool valid = k < q.n_sdom;
     const int term_a = cload(p.dom_term, d);
     const double wa = cload(a.w_src, term_a);
-    const double wb = valid ? a.w_snk[q.sdom_term[k]] : 0.0;
     const uint32_t* rowoff_d = p.dom_rowoff + (size_t)d * sn;
     const int g_begin = cload(p.dom_grp, d);
     const int g_end = cload(p.dom_grp, d + 1);
     const int sg_begin = q.sdom_grp[k];
     const int sg_end = q.sdom_grp[k + 1];
+    (void)g_begin;
 
     // TAB: row l of this wave's table holds A_g = sum_c w_c S[new row of
     // c][:] for group g = g_begin + l (the source dominator's groups); the
@@ -145,10 +178,6 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
       wave_lds_sync();
     }
 
-    double Pre = 1.0, Pim = 0.0;     // prod_f det G_f
-    double Rre = 0.0, Rim = 0.0;     // sum_c w_c rho_c
-    double Sre = 0.0, Sim = 0.0;     // sum_d w_d sigma_d
-    double Kre = 0.0, Kim = 0.0;     // sum over same-block pairs
     bool bad = false;
     int g = g_begin;
     int sg = sg_begin;
@@ -175,14 +204,15 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
         lu<N, true, true, false, true>(vr, vi, dre, dim, pcol, zero);
         lu_inverse_v<N>(vr, vi);
         bad = bad || zero;
-        const double tr = Pre * dre - Pim * dim;
-        Pim = Pre * dim + Pim * dre;
-        Pre = tr;
+        // the first block sets the sums, the others add to them
+        const double2 P = f == 0 ? make_double2(1.0, 0.0) : sums.get(0);
+        sums.set(0, make_double2(P.x * dre - P.y * dim, P.x * dim + P.y * dre));
       }
       // the source groups of flavour f (wave-uniform): sum_c w_c rho_c =
       // sigma . x_r with sigma = sum_c w_c s_c, s_c the child's new row
       int g_f_end = g;
       while (g_f_end < g_end && (cload(p.grp_fr, g_f_end) >> 8) == f) ++g_f_end;
+      double Rre = 0.0, Rim = 0.0;     // this block's sum_c w_c rho_c
       for (int gg = g; gg < g_f_end; ++gg) {
         const int r = cload(p.grp_fr, gg) & 0xff;
         double sr[N], si[N];
@@ -227,7 +257,13 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
       // cc's; where the source dominator has children in
       // this block, the same-block pairs take kappa = G^-1[cc][r] and
       // beta - alpha = s_c . p - S[new row][new column]
+      {
+        const double2 R = f == 0 ? make_double2(0.0, 0.0) : sums.get(1);
+        sums.set(1, make_double2(R.x + Rre, R.y + Rim));
+      }
       const bool src_kids = g_f_end > g;
+      double Sre = 0.0, Sim = 0.0;     // this block's sum_d w_d sigma_d
+      double Kre = 0.0, Kim = 0.0;     // and same-block pair sum
       int sg_f = sg;
       while (sg_f < sg_end && (q.sgrp_fc[sg_f] >> 8) == f) ++sg_f;
       for (int h = sg; h < sg_f; ++h) {
@@ -316,87 +352,173 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
           Kim += wd * tim;
         }
       }
+      {
+        const double2 S2 = f == 0 ? make_double2(0.0, 0.0) : sums.get(2);
+        const double2 K2 = f == 0 ? make_double2(0.0, 0.0) : sums.get(3);
+        sums.set(2, make_double2(S2.x + Sre, S2.y + Sim));
+        sums.set(3, make_double2(K2.x + Kre, K2.y + Kim));
+      }
       g = g_f_end;
       sg = sg_f;
     }
 
-    double vre, vim;
+    // the sink dominator's weight, read here so that it is not held
+    // through the blocks
+    int kk = k;
+    asm volatile("" : "+v"(kk));
+    const double wb = valid ? a.w_snk[q.sdom_term[kk]] : 0.0;
     {
-      const double ar_ = wa + Rre, ai_ = Rim;
-      const double br_ = wb + Sre, bi_ = Sim;
-      const double mr = ar_ * br_ - ai_ * bi_ - Kre;
-      const double mi = ar_ * bi_ + ai_ * br_ - Kim;
-      vre = Pre * mr - Pim * mi;
-      vim = Pre * mi + Pim * mr;
-    }
-
-    // a dominator block with an exactly zero pivot: every pair of the two
-    // partitions by direct LU (source members wave-uniform, sink members
-    // per lane)
-    const bool need = valid && bad;
-    if (__builtin_amdgcn_ballot_w64(need) != 0) {
-      double fre = 0.0, fim = 0.0;
-      // source members: the dominator (ci = cs_begin - 1), then its children
-      const int cs_begin = uniform(p.grp_ptr[g_begin]);
-      const int cs_end = uniform(p.grp_ptr[g_end]);
-      int gsrc = g_begin;
-      for (int ci = cs_begin - 1; ci < cs_end; ++ci) {
-        int fs = -1, rs = -1;
-        uint32_t srow = 0u;
-        double wi = wa;
-        if (ci >= cs_begin) {
-          while (uniform(p.grp_ptr[gsrc + 1]) <= ci) ++gsrc;
-          fs = uniform(p.grp_fr[gsrc] >> 8);
-          rs = uniform(p.grp_fr[gsrc] & 0xff);
-          srow = uniform(p.child_rowoff[ci]);
-          wi = a.w_src[uniform(p.child_term[ci])];
-        }
-        // sink members: the dominator, then the children of its groups
-        const int cd_begin = q.sgrp_ptr[sg_begin];
-        const int cd_end = q.sgrp_ptr[sg_end];
-        int gsnk = sg_begin;
-        for (int cj = cd_begin - 1; cj < cd_end; ++cj) {
-          int fk = -1, ck = -1;
-          uint32_t scol = 0u;
-          double wj = wb;
-          if (cj >= cd_begin) {
-            while (q.sgrp_ptr[gsnk + 1] <= cj) ++gsnk;
-            fk = q.sgrp_fc[gsnk] >> 8;
-            ck = q.sgrp_fc[gsnk] & 0xff;
-            scol = q.schild_coloff[cj];
-            wj = a.w_snk[q.schild_term[cj]];
-          }
-          double Dre = 1.0, Dim = 0.0;
-          for (int f = 0; f < F; ++f) {
-            const int o = p.off[f];
-            uint32_t co[N];
-#pragma unroll
-            for (int c = 0; c < N; ++c) co[c] = q.sdom_coloff[(size_t)(o + c) * pad + k];
-            double dre, dim;
-            block_det2<N>(lds, rowoff_d + o, f == fs ? rs : -1, srow, co, f == fk ? ck : -1,
-                          scol, dre, dim);
-            const double tr = Dre * dre - Dim * dim;
-            Dim = Dre * dim + Dim * dre;
-            Dre = tr;
-          }
-          if (need) {
-            fre += wi * wj * Dre;
-            fim += wi * wj * Dim;
-          }
-        }
-      }
-      if (need) {
-        vre = fre;
-        vim = fim;
-        ++n_fallback;
+      const double2 P = sums.get(0), R = sums.get(1), S2 = sums.get(2), K2 = sums.get(3);
+      const double ar_ = wa + R.x, ai_ = R.y;
+      const double br_ = wb + S2.x, bi_ = S2.y;
+      const double mr = ar_ * br_ - ai_ * bi_ - K2.x;
+      const double mi = ar_ * bi_ + ai_ * br_ - K2.y;
+      // a lane whose dominators have a block with an exactly zero pivot
+      // adds nothing here: two_sided_pairs_tile takes its pairs
+      if (valid && !bad) {
+        acc_re += P.x * mr - P.y * mi;
+        acc_im += P.x * mi + P.y * mr;
       }
     }
-    if (valid) {
-      acc_re += vre;
-      acc_im += vim;
-    }
+    any_bad = any_bad || __builtin_amdgcn_ballot_w64(valid && bad) != 0;
   }
 
+  __shared__ double red[kWavesPerBlock][2];
+  __shared__ int bad_w[kWavesPerBlock];
+  const double s0 = wave_sum(acc_re), s1 = wave_sum(acc_im);
+  if (lane == 0) {
+    red[wave][0] = s0;
+    red[wave][1] = s1;
+    bad_w[wave] = any_bad ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double v = 0.0;
+    if (threadIdx.x < 2) {
+#pragma unroll
+      for (int w = 0; w < kWavesPerBlock; ++w) v += red[w][threadIdx.x];
+    }
+    a.partial[((size_t)t * a.n_blk_t + chunk) * 3 + threadIdx.x] = v;
+  }
+  if (threadIdx.x == 0) {
+    int any = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) any |= bad_w[w];
+    two_sided_flags(a)[(size_t)t * a.n_blk_t + chunk] = any;
+  }
+}
+
+// The lanes of two_sided_tile whose (source dominator, sink dominator)
+// blocks include one with an exactly zero pivot (no inverse, so no update
+// formula): the same chunk of items, for the workgroups that flagged one;
+// each lane refactorises its blocks as two_sided_tile did (same code, same
+// operands, so the same lanes find the zero pivot) and evaluates every pair
+// of the two partitions by direct LU, counted in the plan's fallback
+// counter.  The sums are added to that workgroup's partials.
+template <int N>
+__device__ __forceinline__ void two_sided_pairs_tile(const ContractArgs& a, int t, int chunk,
+                                                     double2* smem) {
+  const PlanView& p = a.plan;
+  const SinkTreeView& q = a.snk;
+  if (two_sided_flags(a)[(size_t)t * a.n_blk_t + chunk] == 0) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = uniform(threadIdx.x / kWave);
+  stage_slice(a.S + (size_t)t * p.M * p.M, smem, p.M, kBlock);
+  __syncthreads();
+  const char* lds = reinterpret_cast<const char*>(smem);
+  double acc_re = 0.0, acc_im = 0.0;
+  uint32_t n_fallback = 0;
+  const int F = p.F;
+  const int pad = q.n_sdom_pad;
+  for (int item = chunk + a.n_blk_t * wave; item < a.n_items;
+       item += a.n_blk_t * kWavesPerBlock) {
+    const int d = uniform(item / a.n_sblk);
+    const int sb = uniform(item - d * a.n_sblk);
+    const int k = sb * kWave + lane;
+    const bool valid = k < q.n_sdom;
+    const uint32_t* rowoff_d = p.dom_rowoff + (size_t)d * p.sn;
+    bool bad = false;
+    for (int f = 0; f < F; ++f) {
+      const int o = p.off[f];
+      uint32_t co[N], ro[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) co[c] = q.sdom_coloff[(size_t)(o + c) * pad + k];
+#pragma unroll
+      for (int m = 0; m < N; ++m) ro[m] = cload(rowoff_d, o + m);
+      double vr[N][N], vi[N][N];
+      int pcol[N];
+      double dre, dim;
+      bool zero;
+      gather<N>(lds, co, ro, vr, vi);
+#pragma unroll
+      for (int j = 0; j < N; ++j) pcol[j] = (int)co[j];
+      lu<N, true, true, false, true>(vr, vi, dre, dim, pcol, zero);
+      bad = bad || zero;
+    }
+    const bool need = valid && bad;
+    if (__builtin_amdgcn_ballot_w64(need) == 0) continue;
+    const int g_begin = cload(p.dom_grp, d);
+    const int g_end = cload(p.dom_grp, d + 1);
+    const int sg_begin = q.sdom_grp[k];
+    const int sg_end = q.sdom_grp[k + 1];
+    const double wa = cload(a.w_src, cload(p.dom_term, d));
+    const double wb = valid ? a.w_snk[q.sdom_term[k]] : 0.0;
+    double fre = 0.0, fim = 0.0;
+    // source members: the dominator (ci = cs_begin - 1), then its children
+    const int cs_begin = cload(p.grp_ptr, g_begin);
+    const int cs_end = cload(p.grp_ptr, g_end);
+    int gsrc = g_begin;
+    for (int ci = cs_begin - 1; ci < cs_end; ++ci) {
+      int fs = -1, rs = -1;
+      uint32_t srow = 0u;
+      double wi = wa;
+      if (ci >= cs_begin) {
+        while (cload(p.grp_ptr, gsrc + 1) <= ci) ++gsrc;
+        fs = cload(p.grp_fr, gsrc) >> 8;
+        rs = cload(p.grp_fr, gsrc) & 0xff;
+        srow = cload(p.child_rowoff, ci);
+        wi = cload(a.w_src, cload(p.child_term, ci));
+      }
+      // sink members: the dominator, then the children of its groups
+      const int cd_begin = q.sgrp_ptr[sg_begin];
+      const int cd_end = q.sgrp_ptr[sg_end];
+      int gsnk = sg_begin;
+      for (int cj = cd_begin - 1; cj < cd_end; ++cj) {
+        int fk = -1, ck = -1;
+        uint32_t scol = 0u;
+        double wj = wb;
+        if (cj >= cd_begin) {
+          while (q.sgrp_ptr[gsnk + 1] <= cj) ++gsnk;
+          fk = q.sgrp_fc[gsnk] >> 8;
+          ck = q.sgrp_fc[gsnk] & 0xff;
+          scol = q.schild_coloff[cj];
+          wj = a.w_snk[q.schild_term[cj]];
+        }
+        double Dre = 1.0, Dim = 0.0;
+        for (int f = 0; f < F; ++f) {
+          const int o = p.off[f];
+          uint32_t co[N];
+#pragma unroll
+          for (int c = 0; c < N; ++c) co[c] = q.sdom_coloff[(size_t)(o + c) * pad + k];
+          double dre, dim;
+          block_det2<N>(lds, rowoff_d + o, f == fs ? rs : -1, srow, co, f == fk ? ck : -1, scol,
+                        dre, dim);
+          const double tr = Dre * dre - Dim * dim;
+          Dim = Dre * dim + Dim * dre;
+          Dre = tr;
+        }
+        if (need) {
+          fre += wi * wj * Dre;
+          fim += wi * wj * Dim;
+        }
+      }
+    }
+    if (need) {
+      acc_re += fre;
+      acc_im += fim;
+      ++n_fallback;
+    }
+  }
   __shared__ double red[kWavesPerBlock][2];
   const double s0 = wave_sum(acc_re), s1 = wave_sum(acc_im);
   if (lane == 0) {
@@ -410,36 +532,55 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
     if (lane == 0 && nf) atomicAdd(a.fallback, (unsigned long long)nf);
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < 2) {
     double v = 0.0;
-    if (threadIdx.x < 2) {
 #pragma unroll
-      for (int w = 0; w < kWavesPerBlock; ++w) v += red[w][threadIdx.x];
-    }
-    a.partial[((size_t)t * a.n_blk_t + chunk) * 3 + threadIdx.x] = v;
+    for (int w = 0; w < kWavesPerBlock; ++w) v += red[w][threadIdx.x];
+    a.partial[((size_t)t * a.n_blk_t + chunk) * 3 + threadIdx.x] += v;
   }
 }
 
-template <int N, bool TAB>
+template <int N>
+__global__ __launch_bounds__(kBlock, 2) void contract_two_sided_pairs_kernel(ContractArgs a) {
+  extern __shared__ double2 smem[];
+  two_sided_pairs_tile<N>(a, blockIdx.y, blockIdx.x, smem);
+}
+
+template <int N, bool TAB, bool PARK>
 __global__ __launch_bounds__(kBlock, 2) void contract_two_sided_kernel(ContractArgs a) {
   extern __shared__ double2 smem[];
-  two_sided_tile<N, TAB>(a, blockIdx.y, blockIdx.x, smem);
+  two_sided_tile<N, TAB, PARK>(a, blockIdx.y, blockIdx.x, smem);
 }
 
 template <int N>
 static hipError_t launch_two_sided_n(const ContractArgs& a, hipStream_t s) {
   dim3 grid(a.n_blk_t, a.T);
+  // the tables (tab_rows > 0) are sized by the caller to fit beside the
+  // slice and the slots within kTwoSidedLdsLimit; without them, the slots
+  // where they fit
   const bool tab = a.tab_rows > 0;
-  const size_t lds = lds_slice_bytes(a.plan.M) +
-                     (tab ? (size_t)kWavesPerBlock * a.tab_rows * a.plan.M * 16 : 0);
-  const void* fn = tab ? reinterpret_cast<const void*>(&contract_two_sided_kernel<N, true>)
-                       : reinterpret_cast<const void*>(&contract_two_sided_kernel<N, false>);
+  const size_t base = lds_slice_bytes(a.plan.M) +
+                      (tab ? (size_t)kWavesPerBlock * a.tab_rows * a.plan.M * 16 : 0);
+  const bool park = tab || base + kTwoSidedSlotBytes <= kTwoSidedLdsLimit;
+  const size_t lds = base + (park ? kTwoSidedSlotBytes : 0);
+  const void* fn = tab    ? reinterpret_cast<const void*>(&contract_two_sided_kernel<N, true, true>)
+                   : park ? reinterpret_cast<const void*>(&contract_two_sided_kernel<N, false, true>)
+                          : reinterpret_cast<const void*>(&contract_two_sided_kernel<N, false, false>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (tab)
-    hipLaunchKernelGGL((contract_two_sided_kernel<N, true>), grid, dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((contract_two_sided_kernel<N, true, true>), grid, dim3(kBlock), lds, s, a);
+  else if (park)
+    hipLaunchKernelGGL((contract_two_sided_kernel<N, false, true>), grid, dim3(kBlock), lds, s, a);
   else
-    hipLaunchKernelGGL((contract_two_sided_kernel<N, false>), grid, dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((contract_two_sided_kernel<N, false, false>), grid, dim3(kBlock), lds, s,
+                       a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t lds2 = lds_slice_bytes(a.plan.M);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&contract_two_sided_pairs_kernel<N>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((contract_two_sided_pairs_kernel<N>), grid, dim3(kBlock), lds2, s, a);
   return hipGetLastError();
 }
 

@@ -49,6 +49,7 @@ def test_pruned_trees_against_oracle(prune):
     ((2, 4, 3), 24, 150, 90, 6, 3),    # three flavours (uneven sizes refused below)
     ((8,), 30, 120, 70, 5, 3),         # one flavour of 8
     ((1, 1), 10, 40, 30, 3, 2),        # 1 x 1 blocks
+    ((4, 4), 72, 80, 60, 4, 3),        # a slice too large for the LDS tables and sums
 ])
 def test_correlator_against_oracle(nf, M, n_src, n_snk, b, depth):
     if len(set(nf)) != 1:
