@@ -37,21 +37,21 @@ SETTLE_S = 0.3              # untimed work before the first timed method
 # HBM bytes per launch of the update-tree kernel on the mid workload, from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script
 # (--copy-probe), each scaled by the same counter's reading for a 256 MiB
-# device copy (fetch x 1.99976, write x 1.0).  Valid only for the kernel
+# device copy (fetch x 1.99973, write x 1.0).  Valid only for the kernel
 # and launch-configuration sources they were measured on (SHA-256 below);
 # null otherwise.
 TRAFFIC = {
     "workload": "mid",
-    "bytes": 7893.1 * 1.99976 * 1024 + 5312.0 * 1024,
+    "bytes": 7897.3 * 1.99973 * 1024 + 5312.0 * 1024,
     "sources": {
         "paper_1411_3691_amd/csrc/contract_kernels.hip":
             "9fbec0acae9e4cc410113541fe0e7dbcf87dd8592a82e48ce87713d28948a851",
         "paper_1411_3691_amd/csrc/lu_device.h":
-            "21f197e72234e5ee4a485bded6b317888a70e29d7c2be9e200832ed2fd87a45a",
+            "905740ed3c6efd9d38d88961bc63339a3272e4b59a6a2f6ae2ffeeb88306414a",
         "paper_1411_3691_amd/csrc/mhc_plan.hip":
-            "272ff9d3bf57d6babd532f2dbe6ec7016c6cb633d950f8c587b09127aa8fa5b5",
+            "be3e290a69bc8b2395ac452c0a71c3f4cba31b7e7a96fb99288f89103cbdc9b9",
         "paper_1411_3691_amd/csrc/contract_kernels.h":
-            "d53228083f7853eb0096367886288e4d9c6c4d122cb0e6e1f141e8a77b923e6d",
+            "63347504110313df497618ffea800757b5fca4d0610713ae8f5c20155ba71011",
     },
 }
 
