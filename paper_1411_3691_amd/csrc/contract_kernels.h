@@ -66,6 +66,23 @@ struct SinkTreeView {
   const int32_t* sgrp_ptr;        // [n_sgroups + 1] child range
   const uint32_t* schild_coloff;  // [n_schildren] new column byte offset
   const int32_t* schild_term;     // [n_schildren] sink term id
+  // The children again, slot-major for one coalesced read per lane: row
+  // srec_base[f] + i of [rows][n_sdom_pad] holds child i of flavour f of
+  // every sink dominator as (new column offset, offset of the column it
+  // replaces, sink term or -1 for padding, 0); srec_cnt[f][sink block] is
+  // the most children of flavour f in the block (the rows it reads).
+  const int4* srec_static;
+  const int32_t* srec_cnt;
+  int32_t srec_base[9];
+  int32_t n_srec;                 // records (rows x n_sdom_pad)
+};
+
+// A sink child as the two-sided kernel reads it in one call: its new
+// column, the column it replaces (byte offsets; 0xffffffff for padding)
+// and its weight (0 for padding).
+struct SinkRec {
+  uint32_t col, ccol;
+  double w;
 };
 
 struct ContractArgs {
@@ -80,6 +97,7 @@ struct ContractArgs {
   int T, n_items, n_blk_t, n_sblk;
   int tab_rows;                   // two-sided: rows of each wave's LDS table of
                                   // aggregated child rows (0: none)
+  SinkRec* srec;                  // two-sided: the sink children's records of this call
   double2* C;                     // outputs, read by the batch reduction only
   double* A;
 };

@@ -42,6 +42,7 @@ struct mhc_plan {
   std::vector<int32_t> snk_idx;
   void* dev_tree2 = nullptr;
   mhc::kern::SinkTreeView view_snk{};
+  mhc::kern::SinkRec* srec_call = nullptr;  // in dev_tree2: the per-call sink records
   int32_t n_sdom = 0, n_sgroups = 0, n_schildren = 0;
   bool set_edges = false;              // the source tree has set edges
   bool rows_built[2] = {false, false}; // multi-row tables: update tree, plain
@@ -492,6 +493,45 @@ mhc_status mhc_plan_attach_sink_tree(mhc_plan* pl, const mhc_tree* st, void* str
     }
   }
   sdom_grp[pad] = (int32_t)sgrp_fc.size();
+  // slot-major child records per flavour (processing order of the sink
+  // dominators), padded with records that match no column
+  const int F = pl->F;
+  const int n_sb = pad / kSinkBlock;
+  std::vector<int32_t> cnt((size_t)F * pad, 0), srec_cnt((size_t)F * n_sb, 0), rbase(9, 0);
+  for (int k = 0; k < nd; ++k)
+    for (int g = st->dom_grp[order[k]]; g < st->dom_grp[order[k] + 1]; ++g)
+      cnt[(size_t)st->grp_f[g] * pad + k] += st->grp_ptr[g + 1] - st->grp_ptr[g];
+  int rows = 0;
+  for (int f = 0; f < F; ++f) {
+    rbase[f] = rows;
+    int mf = 0;
+    for (int b = 0; b < n_sb; ++b) {
+      int m = 0;
+      for (int k = b * kSinkBlock; k < (b + 1) * kSinkBlock; ++k)
+        m = std::max(m, cnt[(size_t)f * pad + k]);
+      srec_cnt[(size_t)f * n_sb + b] = m;
+      mf = std::max(mf, m);
+    }
+    rows += mf;
+  }
+  std::vector<int4> srec((size_t)rows * pad, make_int4(0, (int)0xffffffffu, -1, 0));
+  {
+    std::vector<int32_t> fill((size_t)F * pad, 0);
+    for (int k = 0; k < nd; ++k) {
+      const int kk = order[k];
+      const int dterm = st->dom_order[kk];
+      for (int g = st->dom_grp[kk]; g < st->dom_grp[kk + 1]; ++g) {
+        const int f = st->grp_f[g], c = st->grp_r[g];
+        const uint32_t ccol = (uint32_t)t.idx[(size_t)dterm * sn + t.off[f] + c] * 16u;
+        for (int ci = st->grp_ptr[g]; ci < st->grp_ptr[g + 1]; ++ci) {
+          const int u = st->grp_child[ci];
+          const int i = fill[(size_t)f * pad + k]++;
+          srec[(size_t)(rbase[f] + i) * pad + k] =
+              make_int4((int)((uint32_t)t.idx[(size_t)u * sn + t.off[f] + c] * 16u), (int)ccol, u, 0);
+        }
+      }
+    }
+  }
   std::vector<char> img;
   const size_t o_term = append(img, sdom_term);
   const size_t o_coloff = append(img, sdom_coloff);
@@ -500,8 +540,13 @@ mhc_status mhc_plan_attach_sink_tree(mhc_plan* pl, const mhc_tree* st, void* str
   const size_t o_ptr = append(img, sgrp_ptr);
   const size_t o_ccol = append(img, schild_coloff);
   const size_t o_cterm = append(img, schild_term);
+  const size_t o_srec = append(img, srec);
+  const size_t o_scnt = append(img, srec_cnt);
+  // then room for the per-call records (SinkRec, 16 bytes each)
+  const size_t o_call = (img.size() + 255) & ~size_t(255);
+  const size_t dev_bytes = o_call + srec.size() * sizeof(mhc::kern::SinkRec);
   void* dev = nullptr;
-  e = hipMalloc(&dev, img.size());
+  e = hipMalloc(&dev, dev_bytes);
   if (e != hipSuccess) return fail(MHC_E_OOM, "mhc_plan_attach_sink_tree: device tables");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   e = hipMemcpyAsync(dev, img.data(), img.size(), hipMemcpyHostToDevice, s);
@@ -531,6 +576,11 @@ mhc_status mhc_plan_attach_sink_tree(mhc_plan* pl, const mhc_tree* st, void* str
   v.sgrp_ptr = reinterpret_cast<const int32_t*>(base + o_ptr);
   v.schild_coloff = reinterpret_cast<const uint32_t*>(base + o_ccol);
   v.schild_term = reinterpret_cast<const int32_t*>(base + o_cterm);
+  v.srec_static = reinterpret_cast<const int4*>(base + o_srec);
+  v.srec_cnt = reinterpret_cast<const int32_t*>(base + o_scnt);
+  for (int f = 0; f < 9; ++f) v.srec_base[f] = rbase[f];
+  v.n_srec = (int32_t)srec.size();
+  pl->srec_call = reinterpret_cast<mhc::kern::SinkRec*>(base + o_call);
   pl->n_sdom = nd;
   pl->n_sgroups = (int32_t)sgrp_fc.size();
   pl->n_schildren = (int32_t)schild_term.size();
@@ -659,6 +709,7 @@ static mhc_status contract_impl(mhc_plan* pl, int32_t method, int32_t T, const v
   a.n_blk_t = n_blk_t;
   a.n_sblk = n_sblk;
   a.snk = pl->view_snk;
+  a.srec = pl->srec_call;
   if (two) {
     // per wave, the source dominator's aggregated child rows (one row of M
     // entries per group) beside the slice, where the LDS holds them

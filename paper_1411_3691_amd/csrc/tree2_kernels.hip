@@ -103,6 +103,12 @@ struct RunningSums<false> {
   __device__ void set(int i, double2 v) { r[i] = v; }
 };
 
+// A wave-uniform double moved to scalar registers.
+__device__ __forceinline__ double uniform_f64(double x) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(x)));
+}
+
 // Per (slice, chunk): whether a lane of the chunk met a block with an
 // exactly zero pivot; ints after the workgroup partials.
 __device__ __forceinline__ int* two_sided_flags(const ContractArgs& a) {
@@ -133,7 +139,7 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
     sums.slot = reinterpret_cast<double2*>(reinterpret_cast<char*>(smem) + lds_slice_bytes(p.M) +
                                            (size_t)kWavesPerBlock * a.tab_rows * p.M * 16) +
                 (size_t)threadIdx.x * 4;
-  double acc_re = 0.0, acc_im = 0.0;  // the lane's total over its items
+  double acc_re = 0.0, acc_im = 0.0;  // the wave's total over its items
   bool any_bad = false;  // wave-uniform
   const int F = p.F;
   const int sn = p.sn;
@@ -150,9 +156,6 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
     const uint32_t* rowoff_d = p.dom_rowoff + (size_t)d * sn;
     const int g_begin = cload(p.dom_grp, d);
     const int g_end = cload(p.dom_grp, d + 1);
-    const int sg_begin = q.sdom_grp[k];
-    const int sg_end = q.sdom_grp[k + 1];
-    (void)g_begin;
 
     // TAB: row l of this wave's table holds A_g = sum_c w_c S[new row of
     // c][:] for group g = g_begin + l (the source dominator's groups); the
@@ -180,7 +183,6 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
 
     bool bad = false;
     int g = g_begin;
-    int sg = sg_begin;
     for (int f = 0; f < F; ++f) {
       const int o = p.off[f];
       uint32_t co[N], ro[N];
@@ -264,15 +266,16 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
       const bool src_kids = g_f_end > g;
       double Sre = 0.0, Sim = 0.0;     // this block's sum_d w_d sigma_d
       double Kre = 0.0, Kim = 0.0;     // and same-block pair sum
-      int sg_f = sg;
-      while (sg_f < sg_end && (q.sgrp_fc[sg_f] >> 8) == f) ++sg_f;
-      for (int h = sg; h < sg_f; ++h) {
-        // the changed column's offset: pcol[j] == ccol marks its position
-        const int cc = q.sgrp_fc[h] & 0xff;
-        const uint32_t ccol = q.sdom_coloff[(size_t)(o + cc) * pad + k];
-        for (int ch = q.sgrp_ptr[h]; ch < q.sgrp_ptr[h + 1]; ++ch) {
-          const uint32_t col = q.schild_coloff[ch];
-          const double wd = a.w_snk[q.schild_term[ch]];
+      // the sink children of flavour f, one record per step for every lane
+      // (coalesced; padding records weigh 0 and match no column): pcol[j]
+      // == ccol marks the position of the column the child replaces
+      const int nrec = cload(q.srec_cnt, f * a.n_sblk + sb);
+      const SinkRec* rec = a.srec + (size_t)q.srec_base[f] * pad + k;
+      for (int i_rec = 0; i_rec < nrec; ++i_rec) {
+        {
+          const SinkRec rc = rec[(size_t)i_rec * pad];
+          const uint32_t col = rc.col, ccol = rc.ccol;
+          const double wd = rc.w;
           double tr[N], ti[N];
 #pragma unroll
           for (int i = 0; i < N; ++i) {
@@ -359,7 +362,6 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
         sums.set(3, make_double2(K2.x + Kre, K2.y + Kim));
       }
       g = g_f_end;
-      sg = sg_f;
     }
 
     // the sink dominator's weight, read here so that it is not held
@@ -375,20 +377,21 @@ __device__ __forceinline__ void two_sided_tile(const ContractArgs& a, int t, int
       const double mi = ar_ * bi_ + ai_ * br_ - K2.y;
       // a lane whose dominators have a block with an exactly zero pivot
       // adds nothing here: two_sided_pairs_tile takes its pairs
-      if (valid && !bad) {
-        acc_re += P.x * mr - P.y * mi;
-        acc_im += P.x * mi + P.y * mr;
-      }
+      const bool use = valid && !bad;
+      const double vre = use ? P.x * mr - P.y * mi : 0.0;
+      const double vim = use ? P.x * mi + P.y * mr : 0.0;
+      // the wave's item total, accumulated in scalar registers
+      acc_re = uniform_f64(acc_re + uniform_f64(wave_sum(vre)));
+      acc_im = uniform_f64(acc_im + uniform_f64(wave_sum(vim)));
     }
     any_bad = any_bad || __builtin_amdgcn_ballot_w64(valid && bad) != 0;
   }
 
   __shared__ double red[kWavesPerBlock][2];
   __shared__ int bad_w[kWavesPerBlock];
-  const double s0 = wave_sum(acc_re), s1 = wave_sum(acc_im);
   if (lane == 0) {
-    red[wave][0] = s0;
-    red[wave][1] = s1;
+    red[wave][0] = acc_re;
+    red[wave][1] = acc_im;
     bad_w[wave] = any_bad ? 1 : 0;
   }
   __syncthreads();
@@ -546,6 +549,20 @@ __global__ __launch_bounds__(kBlock, 2) void contract_two_sided_pairs_kernel(Con
   two_sided_pairs_tile<N>(a, blockIdx.y, blockIdx.x, smem);
 }
 
+// The sink children's records of one call: the static ones with the
+// weight of their term (0 for padding).
+__global__ __launch_bounds__(kBlock) void sink_records(const int4* st, const double* w_snk, int n,
+                                                       SinkRec* out) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  const int4 r = st[e];
+  SinkRec o;
+  o.col = (uint32_t)r.x;
+  o.ccol = (uint32_t)r.y;
+  o.w = r.z >= 0 ? w_snk[r.z] : 0.0;
+  out[e] = o;
+}
+
 template <int N, bool TAB, bool PARK>
 __global__ __launch_bounds__(kBlock, 2) void contract_two_sided_kernel(ContractArgs a) {
   extern __shared__ double2 smem[];
@@ -586,6 +603,11 @@ static hipError_t launch_two_sided_n(const ContractArgs& a, hipStream_t s) {
 
 hipError_t launch_contract_two_sided(const ContractArgs& a, int n, double2* C, hipStream_t s) {
   hipError_t e;
+  if (a.snk.n_srec > 0) {
+    hipLaunchKernelGGL(sink_records, dim3((a.snk.n_srec + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       a.snk.srec_static, a.w_snk, a.snk.n_srec, a.srec);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   switch (n) {
 #define MHC_CASE(NN)                     \
   case NN:                               \
