@@ -37,21 +37,21 @@ SETTLE_S = 0.3              # untimed work before the first timed method
 # HBM bytes per launch of the update-tree kernel on the mid workload, from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script
 # (--copy-probe), each scaled by the same counter's reading for a 256 MiB
-# device copy (fetch x 1.99973, write x 1.0).  Valid only for the kernel
+# device copy (fetch x 1.99975, write x 1.0).  Valid only for the kernel
 # and launch-configuration sources they were measured on (SHA-256 below);
 # null otherwise.
 TRAFFIC = {
     "workload": "mid",
-    "bytes": 7897.3 * 1.99973 * 1024 + 5312.0 * 1024,
+    "bytes": 7897.6 * 1.99975 * 1024 + 5312.0 * 1024,
     "sources": {
         "paper_1411_3691_amd/csrc/contract_kernels.hip":
             "9fbec0acae9e4cc410113541fe0e7dbcf87dd8592a82e48ce87713d28948a851",
         "paper_1411_3691_amd/csrc/lu_device.h":
             "905740ed3c6efd9d38d88961bc63339a3272e4b59a6a2f6ae2ffeeb88306414a",
         "paper_1411_3691_amd/csrc/mhc_plan.hip":
-            "be3e290a69bc8b2395ac452c0a71c3f4cba31b7e7a96fb99288f89103cbdc9b9",
+            "f9a4ed751e1cfb8dbd00a756eded95ce7a1d00cd71de4bdd405c9271b8c5a2e0",
         "paper_1411_3691_amd/csrc/contract_kernels.h":
-            "63347504110313df497618ffea800757b5fca4d0610713ae8f5c20155ba71011",
+            "69b507bda7c87dcc9ddb9c8a51f27b26736039c902a045f74f29122b034c9759",
     },
 }
 
