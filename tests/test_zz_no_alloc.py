@@ -52,6 +52,28 @@ def test_noalloc_matches_contract_twice(method):
         assert np.all(np.abs(C1 - C0) <= 1e-9 * A0)
 
 
+def test_noalloc_two_sided_twice():
+    # the two-sided method also leaves a flag per workgroup in the static
+    # scratch; the second call has singular blocks (a zero row of S), so
+    # its flagged workgroups' pairs are added by the direct-LU pass
+    big = W.workload("mid", T=6, n_src=600, n_snk=300)
+    small = W.workload("mid", T=2, M=24, nf=(4, 4), n_src=120, n_snk=60, branching=4, depth=3)
+    small.S[:, 3, :] = 0
+    for w in (big, small):
+        print(f"noalloc/tree2: T={w.T} M={w.M} blocks {w.nf} {len(w.src)}x{len(w.snk)}",
+              flush=True)
+        plan, S, ws, wk = setup(w)
+        plan.attach_sink_tree(mhc.Tree(mhc.Terms(w.snk, w.nf, w.M)))
+        C1, _ = noalloc(plan, "tree2", S, ws, wk, with_scale=False)
+        C0 = mhc.contract(plan, S, ws, wk, "tree2")
+        _, A0 = mhc.contract(plan, S, ws, wk, "tree", with_scale=True)
+        torch.cuda.synchronize()
+        C0, C1, A0 = (x.cpu().numpy() for x in (C0, C1, A0))
+        assert C1.tobytes() == C0.tobytes()
+        assert np.all(np.abs(C1 - C0) <= 1e-9 * A0)
+    assert plan.fallback_count() > 0
+
+
 def test_noalloc_rejects_bad_arguments():
     w = W.workload("mid", T=1, n_src=40, n_snk=30)
     plan, S, ws, wk = setup(w)
