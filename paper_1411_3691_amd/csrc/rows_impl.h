@@ -143,6 +143,7 @@ __device__ __forceinline__ void rows_chunk(ARGS& a, int t, int chunk, double2* s
 #pragma unroll
         for (int q = 0; q < U; ++q) {
           const int e = e0 + q * WB;
+          v[q] = make_double2(0.0, 0.0);
           dst[q] = -1;
           if (e < total) {
             const int r = e / M, c = e - r * M;
